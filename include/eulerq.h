@@ -294,6 +294,8 @@ int eq_grad_reduce(int32_t n_par, int32_t reps, const double *d_f, const double 
  * eq_sim_run on that network alone with the same seed and net_id. */
 typedef struct eq_batch eq_batch;   /* opaque; references (does not own) its networks */
 
+/* A batch of `count` distinct network handles (EQ_EINVAL for a null or repeated handle: a
+ * network holds device tables for one (h, K) at a time). */
 int eq_batch_create(int32_t count, eq_net *const *nets, eq_batch **out);
 /* Frees the batch (graph, descriptors, workspace) after a device synchronisation; its
  * networks stay valid.  NULL is ignored. */
@@ -317,7 +319,10 @@ int eq_batch_layout(const eq_batch *batch, int32_t reps, int64_t *state_off, int
 
 /* Run network k for n_steps[k] steps (host arrays of count entries).  d_states (device int32,
  * total from eq_batch_layout) receives every N_K; d_sums (device int64, or NULL) the tile sums.
- * Asynchronous on `stream`.  Errors as eq_sim_run. */
+ * Asynchronous on `stream`.  A run that does not replay the cached graph first waits for the
+ * device (an earlier run of the batch, on any stream, may still read the descriptors it
+ * replaces); runs of one batch share its workspace, so they must not overlap (the same stream,
+ * or a synchronisation between them).  Errors as eq_sim_run. */
 int eq_batch_run(eq_batch *batch, const eq_batch_desc *desc, const int32_t *n_steps,
                  const uint32_t *net_ids, int32_t *d_states, int64_t *d_sums, void *stream);
 

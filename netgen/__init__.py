@@ -148,6 +148,19 @@ def three_station() -> Network:
                    phase=0.0, name="three_station")
 
 
+def branching() -> Network:
+    """Five stations, feed-forward, every routing row with two or more edges of distinct
+    probabilities: 0 -> {1: .5, 2: .25, 3: .15} (exit .1), 1 -> {3: .4, 4: .3} (exit .3),
+    2 -> {4: .6} (exit .4), 3 -> {4: .5} (exit .5), 4 exits.  Constant arrivals at rate 20
+    into station 0, mu = 1, servers (25, 13, 7, 9, 12): total rates (20, 10, 5, 7, 9.5), loads
+    0.5 to 0.8.  A swapped target or a misordered split changes the total rates."""
+    rows = [[(1, 0.5), (2, 0.25), (3, 0.15)], [(3, 0.4), (4, 0.3)], [(4, 0.6)], [(4, 0.5)], []]
+    row_ptr, col, prob = _csr(5, rows)
+    return Network(n=5, row_ptr=row_ptr, col=col, prob=prob, servers=np.array([25, 13, 7, 9, 12], np.int32),
+                   mu=np.ones(5, np.float32), src=np.array([0], np.int32), lambda0=np.array([20.0], np.float32),
+                   name="branching5")
+
+
 def single_station(lam: float, mu: float, c: int, shape_kind: int = SHAPE_CONST, amp: float = 0.0,
                    period: float = 1.0) -> Network:
     return Network(n=1, row_ptr=np.array([0, 0], dtype=np.int32), col=np.zeros(0, dtype=np.int32),

@@ -8,6 +8,7 @@ cpu_baseline leg may import this package.  The GPU library never uses it.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -45,32 +46,66 @@ class _Net(C.Structure):
                 ("knot_t", C.c_void_p), ("knot_shape", C.c_void_p)]
 
 
+def build_variant(substitutions, out_dir: str, name: str = "liboracle_variant.so") -> str:
+    """Compile a copy of the oracle with textual substitutions [(old, new), ...] applied to
+    euler_oracle.c (each `old` must occur exactly once): the planted-mistake tests use this to
+    check that their pins fail on a wrong oracle.  Returns the library path."""
+    src = open(SOURCES[0]).read()
+    for old, new in substitutions:
+        if src.count(old) != 1:
+            raise ValueError(f"substitution target must occur once: {old!r}")
+        src = src.replace(old, new)
+    os.makedirs(out_dir, exist_ok=True)
+    cpath = os.path.join(out_dir, "euler_oracle_variant.c")
+    with open(cpath, "w") as fh:
+        fh.write(src)
+    out = os.path.join(out_dir, name)
+    subprocess.run(["gcc", *CFLAGS, "-o", out, cpath, SOURCES[1], "-lm"], check=True)
+    return out
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every call of this module to the oracle library at `path` for the duration."""
+    global _lib
+    saved = _lib
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        vp, i32, i64, u32, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
-        L.orc_run.argtypes = [C.POINTER(_Net), i32, i32, f32, i32, u64, u32, i32, vp, vp, vp, vp, vp, vp,
-                              vp, vp, vp, i32]
-        L.orc_tables.argtypes = [C.POINTER(_Net), f32, i32, vp, vp, vp, vp, vp, vp]
-        L.orc_sample_score.argtypes = [i32, i64, u64, u32, u32, u32, u32, i32, i32, f32, f32, vp, vp]
-        L.orc_run_record.argtypes = [C.POINTER(_Net), i32, i32, f32, i32, u64, u32, i32, vp, vp, vp, i32, i32, vp,
-                                     vp, vp, i32]
-        L.orc_sojourn.argtypes = [C.POINTER(_Net), i32, u64, u32, i32, vp, i32, i32, vp, vp, vp, i32, vp, vp, vp]
-        L.orc_lemma3.argtypes = [i32, i32, i32]
-        L.orc_lemma3.restype = f32
-        L.orc_sample.argtypes = [i32, i64, u64, u32, u32, u32, u32, i32, i32, f32, f32, f32, f32, vp]
-        L.orc_math.argtypes = [i32, i64, vp, vp]
-        L.orc_philox_batch.argtypes = [i64, vp, vp, vp]
-        L.orc_get_tables.argtypes = [vp, vp]
-        L.orc_get_tables.restype = None
-        L.orc_philox_batch.restype = None
-        L.des_run.argtypes = [C.POINTER(_Net), C.c_double, i32, u64, i32, vp, i32, vp, vp, vp, vp, vp, vp,
-                              i32]
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+def _load(path: str):
+    L = C.CDLL(path)
+    vp, i32, i64, u32, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
+    L.orc_run.argtypes = [C.POINTER(_Net), i32, i32, f32, i32, u64, u32, i32, vp, vp, vp, vp, vp, vp,
+                          vp, vp, vp, i32]
+    L.orc_tables.argtypes = [C.POINTER(_Net), f32, i32, vp, vp, vp, vp, vp, vp]
+    L.orc_sample_score.argtypes = [i32, i64, u64, u32, u32, u32, u32, i32, i32, f32, f32, vp, vp]
+    L.orc_run_record.argtypes = [C.POINTER(_Net), i32, i32, f32, i32, u64, u32, i32, vp, vp, vp, i32, i32, vp,
+                                 vp, vp, i32]
+    L.orc_sojourn.argtypes = [C.POINTER(_Net), i32, u64, u32, i32, vp, i32, i32, vp, vp, vp, i32, vp, vp, vp]
+    L.orc_lemma3.argtypes = [i32, i32, i32]
+    L.orc_lemma3.restype = f32
+    L.orc_sample.argtypes = [i32, i64, u64, u32, u32, u32, u32, i32, i32, f32, f32, f32, f32, vp]
+    L.orc_math.argtypes = [i32, i64, vp, vp]
+    L.orc_philox_batch.argtypes = [i64, vp, vp, vp]
+    L.orc_get_tables.argtypes = [vp, vp]
+    L.orc_get_tables.restype = None
+    L.orc_philox_batch.restype = None
+    L.des_run.argtypes = [C.POINTER(_Net), C.c_double, i32, u64, i32, vp, i32, vp, vp, vp, vp, vp, vp,
+                          i32]
+    return L
 
 
 def _ptr(a: Optional[np.ndarray]):

@@ -604,6 +604,10 @@ class Batch:
                              None, _stream(stream), C.byref(best)))
         return best.value
 
+    def check(self, stream=None):
+        """eq_batch_check: synchronise the stream and raise on a sticky device flag."""
+        _check(eq_batch_check(self.handle, _stream(stream)))
+
     def split(self, states, sums, reps: int):
         """Per-network views: [(state [n, reps], sums [3, n, tiles]), ...]."""
         so, mo = self.layout(reps)

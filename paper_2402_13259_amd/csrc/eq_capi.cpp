@@ -1170,6 +1170,9 @@ struct eq_batch {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   std::vector<int64_t> gkey;
+  // the descriptors in d_nets may be read by work still queued (a run without a graph on a
+  // stream the library does not wait on): set by every enqueue, cleared by a synchronisation
+  bool nets_in_use = false;
 
   ~eq_batch() { release(); }
   void drop_graph() {
@@ -1224,6 +1227,15 @@ int eq_batch_create(int32_t count, eq_net *const *nets, eq_batch **out) {
   if (count < 1 || !nets) return fail(EQ_EINVAL, "count must be >= 1 and nets non-null");
   for (int32_t k = 0; k < count; ++k)
     if (!nets[k]) return fail(EQ_EINVAL, "nets[%d] is null", k);
+  // a network's device tables exist for one (h, K) at a time, so a handle may appear once
+  try {
+    std::vector<eq_net *> seen(nets, nets + count);
+    std::sort(seen.begin(), seen.end());
+    for (size_t k = 1; k < seen.size(); ++k)
+      if (seen[k] == seen[k - 1]) return fail(EQ_EINVAL, "a network handle appears more than once in the batch");
+  } catch (...) {
+    return fail(EQ_ENOMEM, "host allocation");
+  }
   eq_batch *b = new (std::nothrow) eq_batch();
   if (!b) return fail(EQ_ENOMEM, "host allocation");
   b->nets.assign(nets, nets + count);
@@ -1320,9 +1332,11 @@ int eq_batch_run(eq_batch *b, const eq_batch_desc *d, const int32_t *n_steps, co
   }
   const bool replay = d->use_graph && b->gexec && key == b->gkey;
   if (!replay) {
-    if (b->gexec) {
+    if (b->gexec || b->nets_in_use) {
+      // a replay or an earlier run (on any stream) may still read the descriptors
       if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
       b->drop_graph();
+      b->nets_in_use = false;
     }
     if (!b->d_nets && (e = hipMalloc((void **)&b->d_nets, sizeof(eq::BatchNet) * count)) != hipSuccess)
       return fail(EQ_ENOMEM, "batch descriptor allocation");
@@ -1355,6 +1369,7 @@ int eq_batch_run(eq_batch *b, const eq_batch_desc *d, const int32_t *n_steps, co
     return hipSuccess;
   };
   if (!d->use_graph) {
+    b->nets_in_use = true;
     if ((e = enqueue(st)) != hipSuccess) return hip_fail(e, "batch launch");
     return EQ_OK;
   }

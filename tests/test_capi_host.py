@@ -237,3 +237,19 @@ def test_device_pointer_checks(eb):
         eb._dev(torch.zeros((2, 3), dtype=torch.int32), torch.int32, (2, 3), "x")
     with pytest.raises(TypeError):
         eb._dev(np.zeros((2, 3), np.int32), torch.int32, (2, 3), "x")
+
+
+def test_batch_rejects_repeated_network(eb):
+    """eq_batch_create refuses a handle listed twice (a network keeps device tables for one
+    (h, K) at a time, so a repeated handle with two horizons would read past its tables)."""
+    w = netgen.three_station()
+    a, b = eb.Net(w), eb.Net(w)
+    for handles in ([a, b, a], [b, b]):
+        arr = (C.c_void_p * len(handles))(*[x.handle for x in handles])
+        h = C.c_void_p()
+        assert eb.eq_batch_create(len(handles), arr, C.byref(h)) == eb.EQ_EINVAL
+        assert b"more than once" in eb.eq_last_error() and not h.value
+    arr = (C.c_void_p * 2)(a.handle, b.handle)
+    h = C.c_void_p()
+    assert eb.eq_batch_create(2, arr, C.byref(h)) == 0 and h.value
+    eb.eq_batch_destroy(h)

@@ -163,12 +163,18 @@ def test_layered_full_size_sampled_reps(eb, scheme, kernel):
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_dag1000_full_size_sampled_reps(eb, scheme):
     """Full size (1000 stations, 20000 steps, 4096 replications) in the launch configuration
-    the benchmark times: final states of sampled replications bit-exact."""
+    the benchmark times: final states of sampled replications bit-exact, and the int64 sums of
+    N, (N - m)^+ and D over the whole horizon of one full 64-replication tile (replications
+    2624..2687) bit-exact: the statistics the benchmark reports, after the queues have built
+    up through several arrival peaks."""
     w = netgen.config3()
     net, res, state, sums = gpu_run(eb, w.net, w, scheme, w.K, w.reps, seed=0)
-    rows = np.r_[0:3, 2047:2049, 4095:4096]
+    tile = 41
+    rows = np.r_[0:3, 2047:2049, 4095:4096, tile * 64:(tile + 1) * 64]
     ref = oracle.run(w.net, scheme, w.dt, w.K, 0, rows)
-    assert_same(state, None, ref, rows)
+    assert_same(state, sums, ref, rows, full_tiles=[tile])
+    # the long horizon reaches the queueing branch of Algorithm 3 on most stations
+    assert (ref["sumQ"].sum(0) > 0).mean() > 0.5
 
 
 @pytest.mark.parametrize("scheme", [0, 1])
@@ -281,6 +287,31 @@ def small_batch():
     for w in ws:                      # short horizons keep the test quick; uneven on purpose
         w.T = round(min(w.T, 1.0 + 0.25 * w.net_id) / w.dt) * w.dt
     return ws
+
+
+def test_batch_back_to_back_runs_on_side_stream(eb, small_batch):
+    """Two runs of one batch without a graph, queued back to back on a non-blocking stream
+    with different horizons and no synchronisation between them: each gives the per-network
+    results of its own horizons (the second run's descriptors must not reach the first)."""
+    import torch
+    ws = small_batch
+    nets = [eb.Net(w.net) for w in ws]
+    batch = eb.Batch(nets)
+    reps, dt, ids = ws[0].reps, ws[0].dt, [w.net_id for w in ws]
+    k1 = [w.K for w in ws]
+    k2 = [max(1, k // 3) for k in k1]
+    side = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(side):
+        for ks in (k1, k2):
+            outs.append(batch.run(0, dt, ks, ids, reps, seed=4, use_graph=False, stream=side, check=False))
+    side.synchronize()
+    batch.check()
+    for (states, sums), ks in zip(outs, (k1, k2)):
+        for (st, sm), w, net, k in zip(batch.split(states, sums, reps), ws, nets, ks):
+            ref = eb.simulate(net, 0, dt, k, reps, 4, net_id=w.net_id, kernel=eb.EQ_KERNEL_SWEEP)
+            torch.cuda.synchronize()
+            assert torch.equal(st, ref.state) and torch.equal(sm, ref.sums), (w.name, k)
 
 
 @pytest.mark.parametrize("scheme", [0, 1])
