@@ -46,10 +46,11 @@ class _Net(C.Structure):
                 ("knot_t", C.c_void_p), ("knot_shape", C.c_void_p)]
 
 
-def build_variant(substitutions, out_dir: str, name: str = "liboracle_variant.so") -> str:
+def build_variant(substitutions, out_dir: str, name: str = "liboracle_variant.so", extra_flags=()) -> str:
     """Compile a copy of the oracle with textual substitutions [(old, new), ...] applied to
-    euler_oracle.c (each `old` must occur exactly once): the planted-mistake tests use this to
-    check that their pins fail on a wrong oracle.  Returns the library path."""
+    euler_oracle.c (each `old` must occur exactly once) and optional extra compiler flags: the
+    planted-mistake tests use this to check that their pins fail on a wrong oracle, the
+    sanitizer tests to build it with AddressSanitizer.  Returns the library path."""
     src = open(SOURCES[0]).read()
     for old, new in substitutions:
         if src.count(old) != 1:
@@ -60,7 +61,7 @@ def build_variant(substitutions, out_dir: str, name: str = "liboracle_variant.so
     with open(cpath, "w") as fh:
         fh.write(src)
     out = os.path.join(out_dir, name)
-    subprocess.run(["gcc", *CFLAGS, "-o", out, cpath, SOURCES[1], "-lm"], check=True)
+    subprocess.run(["gcc", *CFLAGS, *extra_flags, "-o", out, cpath, SOURCES[1], "-lm"], check=True)
     return out
 
 

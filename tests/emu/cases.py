@@ -1,0 +1,241 @@
+"""Cases run through the host build of the simulator library (tests/emu/build.py), each in a
+process with the AddressSanitizer runtime preloaded: `python cases.py <case> [args]`.
+
+Every case drives the library through its C ABI exactly as a caller does (network handles,
+run descriptors, caller-owned output buffers; here host arrays stand in for device memory),
+then compares the outputs with the oracle bit for bit.  A sanitizer finding aborts the
+process with its report; a wrong result fails an assertion; "case ok" is printed at the end.
+"""
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path[:0] = [ROOT, os.path.dirname(HERE)]
+
+import netgen  # noqa: E402
+import oracle  # noqa: E402
+from paper_2402_13259_amd import abi  # noqa: E402
+
+LIB = C.CDLL(os.path.join(HERE, "_build", "libeulerq_emu.so"))
+F = abi.configure(LIB)
+LIB.hipemu_nonuniform_readfirstlane.restype = C.c_longlong
+
+
+def ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def check(rc):
+    if rc < 0:
+        raise RuntimeError(f"library error {rc}: {F['eq_last_error']().decode()}")
+    return rc
+
+
+class Net:
+    def __init__(self, net):
+        self.n, self.nnz = int(net.n), int(net.row_ptr[-1])
+        self.keep = [np.ascontiguousarray(net.row_ptr, np.int32), np.ascontiguousarray(net.col, np.int32),
+                     np.ascontiguousarray(net.prob, np.float32), np.ascontiguousarray(net.servers, np.int32),
+                     np.ascontiguousarray(net.mu, np.float32), np.ascontiguousarray(net.src, np.int32),
+                     np.ascontiguousarray(net.lambda0, np.float32)]
+        rp, col, prob, srv, mu, src, lam = self.keep
+        knots = (0, None, None)
+        if getattr(net, "knot_t", None) is not None:
+            self.keep += [np.ascontiguousarray(net.knot_t, np.float64), np.ascontiguousarray(net.knot_shape, np.float64)]
+            knots = (len(net.knot_t), ptr(self.keep[-2]), ptr(self.keep[-1]))
+        arr = abi.eq_arrivals(len(src), ptr(src), ptr(lam), int(net.shape_kind), float(net.amp), float(net.period),
+                              float(net.phase), *knots)
+        self.h = C.c_void_p()
+        check(F["eq_net_create"](self.n, ptr(rp), ptr(col), ptr(prob), ptr(srv), ptr(mu), C.byref(arr),
+                                 C.byref(self.h)))
+        if getattr(net, "staff_start", None) is not None:
+            st = np.ascontiguousarray(net.staff_start, np.int32)
+            sv = np.ascontiguousarray(net.staff_servers, np.int32).reshape(len(st), self.n)
+            self.keep += [st, sv]
+            check(F["eq_net_set_staffing"](self.h, len(st), ptr(st), ptr(sv), int(net.staff_period)))
+
+
+def desc(scheme, dt, K, reps, seed, kernel=abi.EQ_KERNEL_AUTO, **kw):
+    d = dict(dep_mode=0, net_id=0, rep0=0, tile_reps=0, block=0)
+    d.update(kw)
+    return abi.eq_run_desc(scheme, d["dep_mode"], dt, K, seed, d["net_id"], d["rep0"], reps, kernel, d["tile_reps"],
+                           d["block"])
+
+
+def tiles(reps):
+    return (reps + 63) // 64
+
+
+def run(net, d):
+    st = np.zeros((net.n, d.reps), np.int32)
+    sums = np.zeros((3, net.n, tiles(d.reps)), np.int64)
+    check(F["eq_sim_run"](net.h, C.byref(d), None, ptr(st), ptr(sums), None))
+    check(F["eq_sim_check"](net.h, None))
+    return st, sums
+
+
+def assert_run_equals_oracle(w, scheme, dt, K, reps, seed, st, sums):
+    ref = oracle.run(w, scheme, dt, K, seed, np.arange(reps))
+    assert np.array_equal(st.T, ref["final"]), "final states differ from the oracle"
+    for k, name in enumerate(("sumN", "sumQ", "sumD")):
+        for t in range(tiles(reps)):
+            assert np.array_equal(sums[k, :, t], ref[name][64 * t:64 * (t + 1)].sum(0)), (name, t)
+
+
+def staffed(w):
+    start = np.array([0, 30, 70], np.int32)
+    servers = np.stack([w.servers, np.maximum(1, w.servers // 2), w.servers + 3]).astype(np.int32)
+    return w.replace(staff_start=start, staff_servers=servers, staff_period=100)
+
+
+# ---------------------------------------------------------------------------------------------
+def case_record_sojourn(scheme: str, staff: str):
+    """The layered 100-station network, 400 steps, 70 replications (a full tile and a ragged one),
+    a record of steps 40..400 in the layout [step][station][replication], then sojourn walks
+    that start anywhere in the record, the last two recorded intervals included."""
+    scheme, staff = int(scheme), int(staff)
+    w = netgen.config2().net
+    if staff:
+        w = staffed(w)
+    h, K, reps, seed, t0, L = 0.01, 400, 70, 6, 40, 361
+    net = Net(w)
+    d = desc(scheme, h, K, reps, seed, abi.EQ_KERNEL_SWEEP)
+    st = np.zeros((net.n, reps), np.int32)
+    sums = np.zeros((3, net.n, tiles(reps)), np.int64)
+    rN = np.zeros((L, net.n, reps), np.int32)
+    rD = np.zeros((L, net.n, reps), np.int32)
+    rR = np.zeros((L, net.nnz, reps), np.int32)
+    check(F["eq_sim_run_record"](net.h, C.byref(d), None, ptr(st), ptr(sums), t0, L, ptr(rN), ptr(rD), ptr(rR), None))
+    check(F["eq_sim_check"](net.h, None))
+    ref = oracle.run_record(w, scheme, h, K, seed, np.arange(reps), rec_t0=t0, rec_len=L)
+    for name, got in (("N", rN), ("D", rD), ("R", rR)):
+        assert np.array_equal(got.transpose(2, 0, 1), ref[name]), f"record {name} differs from the oracle"
+    st2, sums2 = run(net, d)
+    assert np.array_equal(st2, st) and np.array_equal(sums2, sums), "the recording run changed the run"
+    assert_run_equals_oracle(w, scheme, h, K, reps, seed, st, sums)
+    i0 = np.array([0, 3, 7, 0, 9, 5, 0, 4, 8, 2], np.int32)
+    tau0 = np.array([45, 60, 100, 150, 200, 390, K - 1, K, K - 1, K], np.int32)
+    out = np.zeros((len(i0), reps), np.int32)
+    check(F["eq_sojourn"](net.h, C.byref(d), t0, L, ptr(rN), ptr(rD), ptr(rR), len(i0), ptr(i0), ptr(tau0), ptr(out),
+                          None))
+    Tref = oracle.sojourn(w, scheme, seed, ref, i0, tau0)
+    assert np.array_equal(out.T, Tref), "sojourn samples differ from the oracle"
+    assert (out[-4:] == -1).all()          # walks from the last two intervals leave the record
+    assert (out[:6] > 0).mean() > 0.2
+
+
+def case_kernels(scheme: str):
+    """Both kernels (LDS tile, sweep) on the tandem and on the three-station network with
+    ragged replication counts; the tile kernel at several replications per workgroup."""
+    scheme = int(scheme)
+    for w, dt, K, reps in ((netgen.config1().net, 0.01, 150, 100), (netgen.three_station(), 0.2, 40, 70)):
+        net = Net(w)
+        for kernel, kw in ((abi.EQ_KERNEL_TILE, {}), (abi.EQ_KERNEL_TILE, dict(tile_reps=2, block=64)),
+                           (abi.EQ_KERNEL_SWEEP, {}), (abi.EQ_KERNEL_SWEEP, dict(block=192))):
+            st, sums = run(net, desc(scheme, dt, K, reps, 5, kernel, **kw))
+            assert_run_equals_oracle(w, scheme, dt, K, reps, 5, st, sums)
+
+
+def case_scores():
+    """Score runs (both schemes) and the fp64 cost and gradient reductions."""
+    w = netgen.three_station()
+    dt, K, reps = 0.2, 40, 130
+    hold = np.array([1.0, 2.0, 1.5])
+    net = Net(w)
+    for scheme in (0, 1):
+        d = desc(scheme, dt, K, reps, 3, abi.EQ_KERNEL_SWEEP)
+        st = np.zeros((net.n, reps), np.int32)
+        sq = np.zeros((net.n, reps), np.int64)
+        sc = np.zeros((net.n + len(w.src), reps), np.float32)
+        check(F["eq_sim_run_scores"](net.h, C.byref(d), None, ptr(st), None, ptr(sq), ptr(sc), ptr(sc[net.n:]), None))
+        ref = oracle.run(w, scheme, dt, K, 3, np.arange(reps), scores=True)
+        assert np.array_equal(st.T, ref["final"]) and np.array_equal(sq.T, ref["sumQ"])
+        assert np.array_equal(sc[:net.n].T.view(np.uint32), ref["score_mu"].view(np.uint32))
+        assert np.array_equal(sc[net.n:].T.view(np.uint32), ref["score_lam"].view(np.uint32))
+        f = np.zeros(reps)
+        ms = np.zeros(2)
+        check(F["eq_cost_reduce"](net.n, reps, K, ptr(hold), ptr(sq), ptr(f), ptr(ms), None))
+        fr = oracle.cost_per_rep(ref["sumQ"], hold, K)
+        assert np.allclose(f, fr, rtol=1e-13, atol=0)
+        npar = sc.shape[0]
+        g, se = np.zeros(npar), np.zeros(npar)
+        check(F["eq_grad_reduce"](npar, reps, ptr(f), ptr(ms), ptr(sc), ptr(g), ptr(se), None))
+        rg, rse = oracle.lr_gradient(fr, np.concatenate([ref["score_mu"], ref["score_lam"]], axis=1))
+        assert np.allclose(g, rg, rtol=1e-10, atol=1e-9 * np.abs(rg).max())
+        assert np.allclose(se, rse, rtol=1e-6)
+
+
+def case_batch():
+    """A batch of uneven networks, captured as a graph and replayed twice, and run without a
+    graph: each network's results equal its own run."""
+    sizes = (12, 31, 7, 45, 20)
+    ws = [netgen.Workload(f"dag{n}", netgen.sparse_dag(n, max(1, n // 10), seed=k + 1), dt=0.01, T=1.0, reps=70,
+                          net_id=k + 1) for k, n in enumerate(sizes)]
+    nets = [Net(w.net) for w in ws]
+    arr = (C.c_void_p * len(nets))(*[n.h.value for n in nets])
+    b = C.c_void_p()
+    check(F["eq_batch_create"](len(nets), arr, C.byref(b)))
+    reps, dt = 70, ws[0].dt
+    ks = np.array([max(1, min(w.K, 60 + 13 * i)) for i, w in enumerate(ws)], np.int32)
+    ids = np.array([w.net_id for w in ws], np.uint32)
+    so, mo = np.zeros(len(nets) + 1, np.int64), np.zeros(len(nets) + 1, np.int64)
+    check(F["eq_batch_layout"](b, reps, ptr(so), ptr(mo)))
+    for scheme in (0, 1):
+        for graph in (1, 1, 0):
+            states = np.zeros(int(so[-1]), np.int32)
+            sums = np.zeros(int(mo[-1]), np.int64)
+            bd = abi.eq_batch_desc(scheme, 0, dt, 9, reps, 0, graph)
+            check(F["eq_batch_run"](b, C.byref(bd), ptr(ks), ptr(ids), ptr(states), ptr(sums), None))
+            check(F["eq_batch_check"](b, None))
+            for k, (w, net) in enumerate(zip(ws, nets)):
+                st, sm = run(net, desc(scheme, dt, int(ks[k]), reps, 9, abi.EQ_KERNEL_SWEEP, net_id=int(ids[k])))
+                assert np.array_equal(states[so[k]:so[k + 1]].reshape(net.n, reps), st), (k, scheme, graph)
+                assert np.array_equal(sums[mo[k]:mo[k + 1]].reshape(3, net.n, tiles(reps)), sm), (k, scheme, graph)
+    F["eq_batch_destroy"](b)
+
+
+def case_oracle(lib_path: str):
+    """The oracle itself built with the sanitizers (its every entry point on small inputs),
+    against the ordinary build of the same source."""
+    w, w3 = netgen.config1().net, netgen.three_station()
+    calls = [
+        lambda: oracle.run(w3, 0, 0.2, 40, 2, np.arange(70), scores=True),
+        lambda: oracle.run(w3, 1, 0.2, 40, 2, np.arange(70), dep_mode=1, scores=True),
+        lambda: oracle.run(staffed(w3), 0, 0.2, 40, 2, np.arange(9)),
+        lambda: oracle.run_record(w3, 1, 0.2, 40, 2, np.arange(9), rec_t0=5, rec_len=30),
+        lambda: oracle.tables(w3.with_piecewise_shape([0.0, 0.8, 1.7], [0.4, 3.0, 1.0], 3.1), 0.1, 50),
+        lambda: oracle.des(w, 0.01, 200, 3, np.arange(20), snap_steps=[50, 199]),
+        lambda: oracle.sample(oracle.SMP_BINOMIAL, 2000, i0=100000, f0=0.3),
+        lambda: oracle.sample(oracle.SMP_GENDEP, 2000, i0=9000, i1=8000, f0=1.1, f1=0.005, f2=0.0055, f3=8800.0),
+        lambda: oracle.sample(oracle.SMP_POISSON, 2000, f0=4321.0),
+        lambda: oracle.math_fn(1, np.linspace(-0.9, 10, 1000, dtype=np.float32)),
+    ]
+    plain = [c() for c in calls]
+    rec = oracle.run_record(w3, 0, 0.2, 40, 2, np.arange(9), rec_t0=1, rec_len=40)
+    plain.append(oracle.sojourn(w3, 0, 2, rec, [0, 1, 2], [3, 20, 40]))
+    with oracle.using_library(lib_path):
+        san = [c() for c in calls]
+        rec2 = oracle.run_record(w3, 0, 0.2, 40, 2, np.arange(9), rec_t0=1, rec_len=40)
+        san.append(oracle.sojourn(w3, 0, 2, rec2, [0, 1, 2], [3, 20, 40]))
+    for a, b in zip(plain, san):
+        if isinstance(a, dict):
+            for k in a:
+                if isinstance(a[k], np.ndarray):
+                    assert np.array_equal(a[k], b[k]), k
+        else:
+            assert np.array_equal(a, b)
+
+
+CASES = {"record_sojourn": case_record_sojourn, "kernels": case_kernels, "scores": case_scores, "batch": case_batch,
+         "oracle": case_oracle}
+
+if __name__ == "__main__":
+    name, args = sys.argv[1], sys.argv[2:]
+    CASES[name](*args)
+    n_bad = LIB.hipemu_nonuniform_readfirstlane()
+    assert n_bad == 0, f"{n_bad} readfirstlane operations saw values that differ across the wavefront"
+    print(f"case ok: {name} {' '.join(args)}", flush=True)

@@ -536,8 +536,9 @@ def to_oracle_record(rec, rep_ids):
 
 SOJOURN_FAULT_SKIP = pytest.mark.skip(
     reason="kept off the GPU: a run of this case (with walks started in the last two recorded intervals and a "
-           "since-reverted waiting loop) ended in a GPU memory fault or hung queue; no cause found: a CPU "
-           "emulation of the kernel on the same record shows no out-of-bounds access and oracle-equal results")
+           "waiting loop that was never committed) ended in a GPU memory fault or hung queue, and no cause has been "
+           "shown; the committed code on these inputs runs clean under AddressSanitizer in the host emulation "
+           "(test_emu_sanitized.py::test_record_and_sojourn_sanitized) with results equal to the oracle's")
 
 
 @pytest.mark.parametrize("scheme,staff", [pytest.param(0, False, marks=SOJOURN_FAULT_SKIP), (1, False), (0, True),
