@@ -286,6 +286,31 @@ int eq_cost_reduce(int32_t n, int32_t reps, int32_t n_steps, const double *d_hol
 int eq_grad_reduce(int32_t n_par, int32_t reps, const double *d_f, const double *d_mean_se,
                    const float *d_score, double *d_grad, double *d_se, void *stream);
 
+/* The same gradient with each parameter's score correlated only with the waiting cost of the
+ * stations that parameter can influence: for mu_j, station j and every station reachable
+ * from it along routing edges; for lambda0 of source s, the source station and the stations
+ * reachable from it.  A station outside that set evolves with draws whose laws do not involve
+ * the parameter, so dropping its cost leaves the estimate unbiased and removes its noise:
+ *   g_j = sum_r (f_{j,r} - mean_r f_{j,r}) S[j][r] / (R - 1),
+ *   f_{j,r} = sum_{i reachable from j} hold_i Q[i][r] / K,
+ * with its standard error as for eq_grad_reduce, fp64 in a fixed order.  d_hold device double
+ * [n], d_sumq device int64 [n][reps], d_score device float [n + n_src][reps] (both as written
+ * by eq_sim_run_scores), n_steps = K >= 1, reps >= 2; d_grad, d_se device double
+ * [n + n_src].  The network's tables must live on the current device (its score run made
+ * them).  The first call builds the reach table on the host and uploads it; the reduction's
+ * workspace (about 8 n (n + n_src) + 16 (n + n_src) reps / 64 bytes) is owned by the network
+ * and grows as needed.  Asynchronous on `stream`. */
+/* The reach table the pruned gradient uses: reach[j][i] = 1 when station i is reachable from
+ * parameter j's station along routing edges, itself included (row j < n: station j, the
+ * parameter mu_j; row n + s: source s's station, the parameter lambda0_s), else 0.  reach is a
+ * host array of (n + n_src) n bytes, or NULL to ask for the row count.  Returns n + n_src, or a
+ * negative error code. */
+int eq_net_reach(eq_net *net, uint8_t *reach);
+
+int eq_grad_reduce_reach(eq_net *net, int32_t reps, int32_t n_steps, const double *d_hold,
+                         const int64_t *d_sumq, const float *d_score, double *d_grad, double *d_se,
+                         void *stream);
+
 /* ---- batches of networks ------------------------------------------------------------------
  * Many independent networks of uneven size simulated together: one launch per step covers the
  * station-coherent tasks of every network still running (networks are ordered longest-first so

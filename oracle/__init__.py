@@ -104,6 +104,7 @@ def _load(path: str):
     L.orc_get_tables.argtypes = [vp, vp]
     L.orc_get_tables.restype = None
     L.orc_philox_batch.restype = None
+    L.orc_op_counts.argtypes = [vp, C.c_int]
     L.des_run.argtypes = [C.POINTER(_Net), C.c_double, i32, u64, i32, vp, i32, vp, vp, vp, vp, vp, vp,
                           i32]
     return L
@@ -283,6 +284,60 @@ def lr_gradient(f: np.ndarray, score: np.ndarray) -> tuple[np.ndarray, np.ndarra
     g = prod.sum(axis=0) / (R - 1)
     se = prod.std(axis=0, ddof=1) * R / (R - 1) / np.sqrt(R)
     return g, se
+
+
+def reach_sets(net) -> np.ndarray:
+    """reach[j, i] = True when the cost of station i can depend on parameter j: for j < n
+    (mu_j) the stations reachable from station j along routing edges, station j itself
+    included; for j = n + s (lambda0 of source s) those reachable from station src[s].  A
+    station outside these sets evolves with draws whose laws do not involve the parameter, so
+    its cost has zero covariance with the parameter's score in expectation."""
+    n = int(net.n)
+    adj = [net.col[net.row_ptr[i]:net.row_ptr[i + 1]] for i in range(n)]
+    reach = np.zeros((n + len(net.src), n), bool)
+    for j, start in enumerate(list(range(n)) + [int(s) for s in net.src]):
+        seen = reach[j]
+        stack = [start]
+        seen[start] = True
+        while stack:
+            i = stack.pop()
+            for t in adj[i]:
+                if not seen[t]:
+                    seen[t] = True
+                    stack.append(int(t))
+    return reach
+
+
+def lr_gradient_reach(sumQ: np.ndarray, hold: np.ndarray, K: int, score: np.ndarray,
+                      reach: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Likelihood-ratio gradient with each parameter's score correlated only with the cost of
+    the stations it can reach: g_j = sum_r (f_{j,r} - mean f_j) S_{r,j} / (R - 1) with
+    f_{j,r} = sum_{i in reach_j} hold_i Q_{r,i} / K, in fp64, and its standard error (sample
+    std of the per-replication products over sqrt(R), times R / (R - 1))."""
+    Q = np.asarray(sumQ, np.float64) * (np.asarray(hold, np.float64) / K)[None, :]    # [R, n]
+    F = Q @ np.asarray(reach, np.float64).T                                          # [R, n_par]
+    S = np.asarray(score, np.float64)
+    R = len(F)
+    prod = (F - F.mean(axis=0)) * S
+    g = prod.sum(axis=0) / (R - 1)
+    se = prod.std(axis=0, ddof=1) * R / (R - 1) / np.sqrt(R)
+    return g, se
+
+
+OP_EVENTS = ["station_step", "philox", "uniform", "pois_inv", "pois_inv_step", "ptrs", "ptrs_try", "ptrs_slow",
+             "bin_inv", "bin_inv_step", "btrs", "btrs_try", "btrs_slow", "bin_prep", "gamma", "gamma_polar",
+             "gamma_try", "gamma_slow", "expm1", "depart", "edge", "push"]
+
+
+def op_counts(reset: bool = True) -> dict:
+    """Event totals of the oracle's runs since the last reset (see the event list in
+    euler_oracle.c): the algorithm's Philox blocks, sampler setups, search steps, rejection
+    attempts, routed edges and station-steps."""
+    L = lib()
+    out = np.zeros(64, np.int64)
+    k = L.orc_op_counts(_ptr(out), int(bool(reset)))
+    assert k == len(OP_EVENTS)
+    return {name: int(v) for name, v in zip(OP_EVENTS, out[:k])}
 
 
 def math_fn(kind: int, x: np.ndarray) -> np.ndarray:

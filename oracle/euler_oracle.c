@@ -74,6 +74,59 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Event counters (instrumentation only: they change no result).  Every thread */
+/* counts the algorithm's events in its own array; a run adds the arrays of its */
+/* worker threads into the totals that orc_op_counts reads.                     */
+/* ------------------------------------------------------------------------- */
+enum {
+    EV_STATION_STEP,   /* (replication, station, step) updates */
+    EV_PHILOX,         /* Philox4x32-10 blocks generated */
+    EV_UNIFORM,        /* uniforms used */
+    EV_POIS_INV,       /* Poisson draws by inversion (lam < 10) */
+    EV_POIS_INV_STEP,  /*   their search steps */
+    EV_PTRS,           /* Poisson draws by PTRS */
+    EV_PTRS_TRY,       /*   attempts */
+    EV_PTRS_SLOW,      /*   attempts that reach the logarithmic test */
+    EV_BIN_INV,        /* binomial draws by inversion (n p < 40) */
+    EV_BIN_INV_STEP,   /*   their search steps */
+    EV_BTRS,           /* binomial draws by BTRS */
+    EV_BTRS_TRY,       /*   attempts */
+    EV_BTRS_SLOW,      /*   attempts that reach the logarithmic test */
+    EV_BIN_PREP,       /* binomials whose probability is computed in the step (x > m branch) */
+    EV_GAMMA,          /* gamma (Erlang) draws */
+    EV_GAMMA_POLAR,    /*   polar-method tries (pairs of uniforms) */
+    EV_GAMMA_TRY,      /*   attempts with a normal */
+    EV_GAMMA_SLOW,     /*   attempts that reach the logarithmic test */
+    EV_EXPM1,          /* 1 - e^{-mu (h - T)} of the T <= h branch */
+    EV_DEPART,         /* departure draws (x > 0) */
+    EV_EDGE,           /* routing edges drawn */
+    EV_PUSH,           /* routed counts pushed (nonzero) */
+    EV_COUNT
+};
+static _Thread_local int64_t tl_ev[EV_COUNT];
+static int64_t g_ev[EV_COUNT];
+static pthread_mutex_t g_ev_lock = PTHREAD_MUTEX_INITIALIZER;
+#define EV(e) (tl_ev[e] += 1)
+
+static void ev_flush(void)
+{
+    pthread_mutex_lock(&g_ev_lock);
+    for (int e = 0; e < EV_COUNT; ++e) g_ev[e] += tl_ev[e];
+    pthread_mutex_unlock(&g_ev_lock);
+    memset(tl_ev, 0, sizeof tl_ev);
+}
+
+/* Event totals of the runs since the last reset (out[EV_COUNT]); reset clears them. */
+int orc_op_counts(int64_t *out, int reset)
+{
+    pthread_mutex_lock(&g_ev_lock);
+    if (out) memcpy(out, g_ev, sizeof g_ev);
+    if (reset) memset(g_ev, 0, sizeof g_ev);
+    pthread_mutex_unlock(&g_ev_lock);
+    return EV_COUNT;
+}
+
 /* One uniform stream per (replication, station, step, substream).  The Philox   */
 /* key is (low 32 bits of seed, high 32 bits of seed XOR network id); the        */
 /* counter is (rep, station, step-1, substream<<24 | block).  Words are consumed */
@@ -112,6 +165,7 @@ static uint32_t us_next_u32(ustream *s)
         }
         s->ctr[3] = (s->sub << 24) | s->block;
         orc_philox4x32_10(s->ctr, s->key, s->buf);
+        EV(EV_PHILOX);
         s->block += 1;
         s->idx = 0;
     }
@@ -125,7 +179,7 @@ float orc_u01(uint32_t x)
     return (float)j * 0x1p-24f;
 }
 
-static float us_u01(ustream *s) { return orc_u01(us_next_u32(s)); }
+static float us_u01(ustream *s) { EV(EV_UNIFORM); return orc_u01(us_next_u32(s)); }
 
 /* ------------------------------------------------------------------------- */
 /* fp32 elementary functions from their series (no libm in the samplers).      */
@@ -300,11 +354,13 @@ int32_t orc_poisson(float lam, ustream *S)
 {
     if (!(lam > 0.0f)) return 0;
     if (lam < 10.0f) {
+        EV(EV_POIS_INV);
         float p = orc_expf(-lam);
         float F = p;
         float u = us_u01(S);
         int32_t k = 0;
         while (u > F && k < POIS_INV_MAX) {
+            EV(EV_POIS_INV_STEP);
             k += 1;
             p = p * (lam * INV[k]);
             float Fn = F + p;
@@ -322,13 +378,16 @@ int32_t orc_poisson(float lam, ustream *S)
     float two_a = 2.0f * a;
     float invalpha = 1.1239f + 1.1328f / (b - 3.4f);
     float vr = 0.9277f - 3.6224f / (b - 2.0f);
+    EV(EV_PTRS);
     for (int it = 0; it < REJECT_CAP; ++it) {
+        EV(EV_PTRS_TRY);
         float U = us_u01(S) - 0.5f;
         float V = us_u01(S);
         float us = 0.5f - fabsf(U);
         float kf = floorf((two_a / us + b) * U + (lam + 0.43f));
         if (us >= 0.07f && V <= vr) return (int32_t)kf;
         if (kf < 0.0f || (us < 0.013f && V > us)) continue;
+        EV(EV_PTRS_SLOW);
         /* ln f(k) = k ln lam - lam - ln k!, with ln k! by the Stirling series:      */
         /*   = (k+1-lam) - (k+1/2) log1p((k+1-lam)/lam) - ln(lam)/2 - ln(2pi)/2 - fc(k) */
         float lhs = orc_logf(V * invalpha / (a / (us * us) + b));
@@ -353,7 +412,9 @@ static int32_t binom_inversion(int32_t n, float p, ustream *S)
     float F = f;
     float u = us_u01(S);
     int32_t k = 0;
+    EV(EV_BIN_INV);
     while (u > F && k < n && k < BINOM_INV_MAX) {
+        EV(EV_BIN_INV_STEP);
         k += 1;
         f = f * (g * INV[k] - r);                     /* f_k = f_{k-1} (n-k+1)/k p/q */
         float Fn = F + f;
@@ -389,7 +450,9 @@ static int32_t binom_btrs(int32_t n, float p, ustream *S)
     float hm = (mf + 0.5f) * orc_log1pf(dm / rnm) + orc_stirling_fc(m) + orc_stirling_fc(n - m);
     /* a mode of 2^24 or more: fp32 cannot represent the values exactly (overflow flag) */
     if (m >= (1 << 24) && S->overflow) *S->overflow = 1;
+    EV(EV_BTRS);
     for (int it = 0; it < REJECT_CAP; ++it) {
+        EV(EV_BTRS_TRY);
         float u = us_u01(S) - 0.5f;
         float v = us_u01(S);
         float us = 0.5f - fabsf(u);
@@ -398,6 +461,7 @@ static int32_t binom_btrs(int32_t n, float p, ustream *S)
         if (kf < 0.0f || kf > nf) continue;
         int32_t k = (int32_t)kf;
         if (k > n) continue;               /* nf may round n up when n >= 2^24 */
+        EV(EV_BTRS_SLOW);
         float lhs = orc_logf(v * alpha / (a / (us * us) + b));
         float nk = nf - kf + 1.0f;
         /* ln f(k)/f(m) by the Stirling series; ln(nm/nk) = log1p((k-m)/nk). */
@@ -429,9 +493,12 @@ float orc_gamma_int(int32_t k, ustream *S)
 {
     float d = (float)k - 0x1.555556p-2f;   /* k - 1/3 */
     float c = 1.0f / sqrtf(9.0f * d);
+    EV(EV_GAMMA);
     for (int it = 0; it < REJECT_CAP; ++it) {
         float x1, x2, s;
+        EV(EV_GAMMA_TRY);
         do {
+            EV(EV_GAMMA_POLAR);
             x1 = 2.0f * us_u01(S) - 1.0f;
             x2 = 2.0f * us_u01(S) - 1.0f;
             s = x1 * x1 + x2 * x2;
@@ -443,6 +510,7 @@ float orc_gamma_int(int32_t k, ustream *S)
         float u = us_u01(S);
         float z2 = z * z;
         if (u < 1.0f - 0.0331f * (z2 * z2)) return d * v;
+        EV(EV_GAMMA_SLOW);
         if (orc_logf(u) < 0.5f * z2 + d * ((1.0f - v) + orc_logf(v))) return d * v;
     }
     if (S->overflow) *S->overflow = 1;
@@ -467,6 +535,7 @@ int32_t orc_gendep(int32_t x, int32_t m, float mu, float dt, float pdep, float r
 {
     if (score) *score = 0.0f;
     if (x <= 0) return 0;
+    EV(EV_DEPART);
     if (x <= m) {
         int32_t D = orc_binomial(x, pdep, S);
         if (score) *score = (float)D * kap - (float)(x - D) * dt;
@@ -476,10 +545,12 @@ int32_t orc_gendep(int32_t x, int32_t m, float mu, float dt, float pdep, float r
     float T = orc_gamma_int(k, S) / rate;
     float sc = (float)k / mu - (float)m * T;
     int32_t D;
+    EV(EV_BIN_PREP);
     if (T > dt) {
         D = orc_binomial(k - 1, dt / T, S);
     } else {
         float s = dt - T;
+        EV(EV_EXPM1);
         float p2 = -orc_expm1f(-(mu * s));
         int32_t Dp = orc_binomial(m, p2, S);
         sc = sc - (float)(m - Dp) * s;
@@ -742,7 +813,9 @@ static void route(const run_ctx *c, int32_t i, int32_t D, int32_t tau, uint32_t 
     us_init(&S, c->seed, c->net_id, rep, (uint32_t)i, (uint32_t)(tau - 1), SUB_ROUTE, ovf);
     int32_t rem = D;
     for (int32_t e = net->row_ptr[i]; e < net->row_ptr[i + 1] && rem > 0; ++e) {
+        EV(EV_EDGE);
         int32_t R = orc_binomial(rem, c->q[e], &S);
+        if (R) EV(EV_PUSH);
         Ain[net->col[e]] += R;
         if (Rrow) Rrow[e] = R;
         rem -= R;
@@ -828,8 +901,10 @@ static void *worker(void *arg)
         pthread_mutex_unlock(&c->lock);
         if (slot >= c->n_reps) break;
         simulate_rep(c, slot, buf, buf + n, buf + 2 * n, buf + 3 * n);
+        tl_ev[EV_STATION_STEP] += (int64_t)n * c->K;
     }
     free(buf);
+    ev_flush();
     return NULL;
 }
 

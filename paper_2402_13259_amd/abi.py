@@ -16,7 +16,7 @@ EXPORTS = ["eq_net_create", "eq_net_destroy", "eq_net_set_staffing", "eq_net_set
            "eq_sim_run", "eq_sim_tune", "eq_sim_run_pair", "eq_stats_reduce", "eq_stats_reduce_pair",
            "eq_sim_run_record", "eq_sojourn", "eq_sim_check", "eq_batch_create", "eq_batch_destroy",
            "eq_batch_layout", "eq_batch_run", "eq_batch_tune", "eq_batch_check", "eq_sim_run_scores", "eq_cost_reduce",
-           "eq_grad_reduce", "eq_selftest_math", "eq_selftest_sample", "eq_selftest_score", "eq_selftest_valu_peak", "eq_selftest_philox",
+           "eq_grad_reduce", "eq_grad_reduce_reach", "eq_net_reach", "eq_selftest_math", "eq_selftest_sample", "eq_selftest_score", "eq_selftest_valu_peak", "eq_selftest_philox",
            "eq_last_error"]
 
 
@@ -71,6 +71,8 @@ _sig = {
     "eq_sim_run_scores": ([_vp, C.POINTER(eq_run_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "eq_cost_reduce": ([_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "eq_grad_reduce": ([_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "eq_grad_reduce_reach": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "eq_net_reach": ([_vp, _vp], C.c_int),
     "eq_selftest_score": ([_i32, _i64, _u64, _u32, _u32, _u32, _u32, _i32, _i32, _f32, _f32, _vp, _vp, _vp],
                           C.c_int),
     "eq_selftest_valu_peak": ([_i32, _i32, _vp, _vp], C.c_int),

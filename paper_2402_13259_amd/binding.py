@@ -118,6 +118,13 @@ class Net:
         sv = np.ascontiguousarray(servers, dtype=np.int32).reshape(len(st), self.n)
         _check(eq_net_set_staffing(self.handle, len(st), _ptr(st), _ptr(sv), int(period)))
 
+    def reach(self) -> np.ndarray:
+        """eq_net_reach: bool [n + n_src, n], row j the stations parameter j can influence."""
+        rows = _check(eq_net_reach(self.handle, None))
+        out = np.zeros((rows, self.n), np.uint8)
+        _check(eq_net_reach(self.handle, _ptr(out)))
+        return out.astype(bool)
+
     def close(self):
         """eq_net_destroy (waits for queued device work first); later calls do nothing."""
         if getattr(self, "handle", None):
@@ -259,6 +266,23 @@ def grad_reduce(f, mean_se, score, stream=None):
     se = torch.empty(n_par, dtype=torch.float64, device=score.device)
     _check(eq_grad_reduce(int(n_par), int(reps), _ptr(f), _ptr(mean_se), _ptr(score), _ptr(g), _ptr(se),
                           _stream(stream)))
+    return g, se
+
+
+def grad_reduce_reach(net: Net, hold, sumq, score, K: int, stream=None):
+    """(grad [n_par] float64, se [n_par] float64) from eq_grad_reduce_reach: each parameter's
+    score against the waiting cost of the stations it can reach."""
+    import torch
+    _dev(score, torch.float32, None, "score")
+    if score.dim() != 2 or score.shape[0] != net.n + net.n_src:
+        raise ValueError("score must be [n + n_src, reps]")
+    n_par, reps = score.shape
+    _dev(sumq, torch.int64, (net.n, reps), "sumq")
+    _dev(hold, torch.float64, (net.n,), "hold")
+    g = torch.empty(n_par, dtype=torch.float64, device=score.device)
+    se = torch.empty(n_par, dtype=torch.float64, device=score.device)
+    _check(eq_grad_reduce_reach(net.handle, int(reps), int(K), _ptr(hold), _ptr(sumq), _ptr(score), _ptr(g), _ptr(se),
+                                _stream(stream)))
     return g, se
 
 

@@ -128,6 +128,12 @@ struct eq_net {
   size_t ws_cap = 0;
   int32_t *d_soj = nullptr;    // sojourn sample table (i0, tau0)
   size_t soj_cap = 0;
+  // reachability-pruned gradient: reach[j][i] for the n + n_src parameters (host, made at the
+  // first such reduction), its device copy and the reduction's workspace
+  std::vector<uint8_t> reach;
+  unsigned char *d_reach = nullptr;
+  double *d_gws = nullptr;
+  size_t gws_cap = 0;
   size_t g_cap = 0;
   bool dev_valid = false;
   uint64_t tables_gen = 0;   // bumped at every rebuild of the device tables (batch graph key)
@@ -145,8 +151,10 @@ struct eq_net {
       (void)hipFree(d_order); (void)hipFree(d_level_ptr); (void)hipFree(d_heavy); (void)hipFree(d_flags);
       (void)hipFree(d_segidx); (void)hipFree(d_seg_m); (void)hipFree(d_seg_rate); (void)hipFree(d_soj);
       (void)hipFree(d_ring_b); (void)hipFree(d_ring_f); (void)hipFree(d_ws);
+      (void)hipFree(d_reach); (void)hipFree(d_gws);
       if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
     }
+    d_reach = nullptr; d_gws = nullptr; gws_cap = 0;
     d_sp = nullptr; d_dep = nullptr; d_scp = nullptr; d_edges = nullptr; d_g = nullptr; d_order = nullptr; d_level_ptr = nullptr; d_heavy = nullptr;
     d_segidx = nullptr; d_seg_m = nullptr; d_seg_rate = nullptr; d_soj = nullptr; soj_cap = 0;
     d_flags = nullptr; d_ring_b = nullptr; d_ring_f = nullptr; d_ws = nullptr; ws_cap = 0;
@@ -280,6 +288,30 @@ void compute_rings(eq_net &net) {
     off += depth[i];
   }
   net.ring_f_slots = off;
+}
+
+// reach[j][i] = 1 when station i is reachable from parameter j's station along routing edges
+// (itself included): station j for mu_j (j < n), the source's station for lambda0 (j = n + s).
+void compute_reach(eq_net &net) {
+  const int32_t n = net.n;
+  const size_t n_par = (size_t)n + net.src_list.size();
+  net.reach.assign(n_par * (size_t)n, 0);
+  std::vector<int32_t> stack;
+  for (size_t j = 0; j < n_par; ++j) {
+    uint8_t *row = net.reach.data() + j * (size_t)n;
+    const int32_t start = j < (size_t)n ? (int32_t)j : net.src_list[j - n];
+    row[start] = 1;
+    stack.assign(1, start);
+    while (!stack.empty()) {
+      const int32_t i = stack.back();
+      stack.pop_back();
+      for (int32_t e = net.row_ptr[i]; e < net.row_ptr[i + 1]; ++e)
+        if (!row[net.col[e]]) {
+          row[net.col[e]] = 1;
+          stack.push_back(net.col[e]);
+        }
+    }
+  }
 }
 
 // Milliseconds of GPU time `fn` enqueues on `st` (events on the same stream).
@@ -678,6 +710,17 @@ int eq_net_tables(const eq_net *net, float dt, int32_t K, float *q, float *pdep,
   return EQ_OK;
 }
 
+int eq_net_reach(eq_net *net, uint8_t *reach) {
+  if (!net) return fail(EQ_EINVAL, "null network");
+  try {
+    if (net->reach.empty()) compute_reach(*net);
+  } catch (...) {
+    return fail(EQ_ENOMEM, "host allocation");
+  }
+  if (reach) std::copy(net->reach.begin(), net->reach.end(), reach);
+  return net->n + (int)net->src_list.size();
+}
+
 int eq_net_levels(const eq_net *net, int32_t *level) {
   if (!net) return fail(EQ_EINVAL, "null network");
   if (!net->index_dag) return fail(EQ_ENOTDAG, "network has an edge i -> j with j <= i");
@@ -931,6 +974,50 @@ int eq_grad_reduce(int32_t n_par, int32_t reps, const double *d_f, const double 
   int rc = ensure_device(&dev);
   if (rc) return rc;
   hipError_t e = eq::launch_grad(d_f, d_mean_se, d_score, reps, n_par, d_grad, d_se, (hipStream_t)stream);
+  return e == hipSuccess ? EQ_OK : hip_fail(e, "gradient launch");
+}
+
+int eq_grad_reduce_reach(eq_net *net, int32_t reps, int32_t n_steps, const double *d_hold, const int64_t *d_sumq,
+                         const float *d_score, double *d_grad, double *d_se, void *stream) {
+  if (!net) return fail(EQ_EINVAL, "null network");
+  if (reps < 2 || n_steps < 1) return fail(EQ_EINVAL, "reps must be >= 2 and n_steps >= 1");
+  if (!d_hold || !d_sumq || !d_score || !d_grad || !d_se) return fail(EQ_EINVAL, "null argument");
+  int dev = 0;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  if (net->device != dev)
+    return fail(EQ_EINVAL, "the network has no tables on device %d: reduce on the device its score run used", dev);
+  const int n = net->n, n_par = net->n + (int)net->src_list.size();
+  hipError_t e;
+  try {
+    if (net->reach.empty()) compute_reach(*net);
+  } catch (...) {
+    return fail(EQ_ENOMEM, "host allocation");
+  }
+  if (!net->d_reach) {
+    if ((e = hipMalloc((void **)&net->d_reach, net->reach.size())) != hipSuccess) {
+      net->d_reach = nullptr;
+      return fail(EQ_ENOMEM, "reach table: %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(net->d_reach, net->reach.data(), net->reach.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+      (void)hipFree(net->d_reach);
+      net->d_reach = nullptr;
+      return hip_fail(e, "upload reach table");
+    }
+  }
+  const size_t ws = eq::grad_reach_workspace_bytes(n, n_par, reps);
+  if (ws > net->gws_cap) {
+    // an earlier reduction on any stream may still use the old workspace
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    (void)hipFree(net->d_gws);
+    net->d_gws = nullptr;
+    net->gws_cap = 0;
+    if ((e = hipMalloc((void **)&net->d_gws, ws)) != hipSuccess)
+      return fail(EQ_ENOMEM, "gradient workspace of %zu bytes: %s", ws, hipGetErrorString(e));
+    net->gws_cap = ws;
+  }
+  e = eq::launch_grad_reach(net->d_reach, d_hold, reinterpret_cast<const long long *>(d_sumq), d_score, n, n_par,
+                            reps, n_steps, net->d_gws, d_grad, d_se, (hipStream_t)stream);
   return e == hipSuccess ? EQ_OK : hip_fail(e, "gradient launch");
 }
 

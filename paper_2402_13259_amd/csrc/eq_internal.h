@@ -138,6 +138,11 @@ hipError_t launch_cost(const double *hold, const long long *sumq, int n, int rep
 hipError_t launch_grad(const double *f, const double *mean_se, const float *score, int reps, int n_par,
                        double *grad, double *se, hipStream_t st);
 hipError_t launch_sweep_pair(const PairArgs &a, int wpb, hipStream_t st);
+// Reachability-pruned gradient: reach [n_par][n] bytes, workspace of grad_reach_workspace_bytes.
+size_t grad_reach_workspace_bytes(int n, int n_par, int reps);
+hipError_t launch_grad_reach(const unsigned char *reach, const double *hold, const long long *sumq,
+                             const float *score, int n, int n_par, int reps, int K, double *ws, double *grad,
+                             double *se, hipStream_t st);
 
 // Sojourn sampling over a recorded path (Algorithm 4).
 struct SojournArgs {

@@ -5,9 +5,16 @@
 where N is the Euler chain (backward or forward scheme) with per-server service rates mu and
 external base rates lambda0.  The forward pass is one score run of the HIP library (the
 simulation plus the per-replication sums of the likelihood-ratio scores of its Poisson and
-binomial/Erlang draws) and the fp64 cost reduction; the backward pass is the library's fp64
-covariance kernel, grad_j = sum_r (f_r - mean f) S_{j,r} / (R - 1).  The simulation's integer
-path is the one a plain run takes: the same draws give the same states.
+binomial/Erlang draws) and the fp64 cost reduction; the backward pass is one of the library's
+fp64 covariance reductions:
+
+* "reach" (default): parameter j's score against the cost of the stations it can reach,
+  grad_j = sum_r (f_{j,r} - mean f_j) S_{j,r} / (R - 1), f_{j,r} = sum_{i reachable from j}
+  hold_i Q_{i,r} / K.  Stations outside that set do not depend on the parameter, so this is
+  unbiased and leaves out their noise.
+* "full": every score against the whole cost, grad_j = sum_r (f_r - mean f) S_{j,r} / (R - 1).
+
+The simulation's integer path is the one a plain run takes: the same draws give the same states.
 
 Only argument marshalling happens here; every step runs in the library.
 """
@@ -36,6 +43,7 @@ class CostProblem:
     seed: int = 0
     dep_mode: int = eb.EQ_DEP_EXACT
     net_id: int = 0
+    estimator: str = "reach"     # "reach" (pruned to reachable stations) or "full"
     # filled by each forward / backward pass: standard errors of J and of the gradient
     last: dict = field(default_factory=dict)
 
@@ -58,7 +66,9 @@ class ExpectedCost(torch.autograd.Function):
         f, mean_se = eb.cost_reduce(hold, res.sumq, p.K)
         J = mean_se[0] + p.staffing()
         p.last = {"J_se": mean_se[1]}
-        ctx.save_for_backward(f, mean_se, res.score)
+        if p.estimator not in ("reach", "full"):
+            raise ValueError(f"estimator must be 'reach' or 'full', not {p.estimator!r}")
+        ctx.save_for_backward(f, mean_se, res.score, res.sumq, hold)
         ctx.n = net.n
         ctx.net = net                      # keeps the device tables alive until backward
         ctx.problem = p
@@ -67,8 +77,12 @@ class ExpectedCost(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gJ: torch.Tensor):
-        f, mean_se, score = ctx.saved_tensors
-        g, se = eb.grad_reduce(f, mean_se, score)
+        f, mean_se, score, sumq, hold = ctx.saved_tensors
+        p = ctx.problem
+        if p.estimator == "reach":
+            g, se = eb.grad_reduce_reach(ctx.net, hold, sumq, score, p.K)
+        else:
+            g, se = eb.grad_reduce(f, mean_se, score)
         ctx.problem.last.update(grad=g, grad_se=se)
         n = ctx.n
         (mdt, mdev), (ldt, ldev) = ctx.in_meta

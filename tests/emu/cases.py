@@ -167,6 +167,26 @@ def case_scores():
         rg, rse = oracle.lr_gradient(fr, np.concatenate([ref["score_mu"], ref["score_lam"]], axis=1))
         assert np.allclose(g, rg, rtol=1e-10, atol=1e-9 * np.abs(rg).max())
         assert np.allclose(se, rse, rtol=1e-6)
+        check(F["eq_grad_reduce_reach"](net.h, reps, K, ptr(hold), ptr(sq), ptr(sc), ptr(g), ptr(se), None))
+        rg, rse = oracle.lr_gradient_reach(ref["sumQ"], hold, K, np.concatenate([ref["score_mu"], ref["score_lam"]],
+                                                                                axis=1), oracle.reach_sets(w))
+        assert np.allclose(g, rg, rtol=1e-10, atol=1e-9 * np.abs(rg).max())
+        assert np.allclose(se, rse, rtol=1e-6)
+    # a larger network: several parameter and replication tiles, ragged at both ends
+    w = netgen.sparse_dag(150, 9, seed=21, c_range=(2, 12))
+    hold = np.linspace(1.0, 3.0, w.n)
+    net = Net(w)
+    K, reps = 30, 200
+    d = desc(0, 0.05, K, reps, 4, abi.EQ_KERNEL_SWEEP)
+    st = np.zeros((net.n, reps), np.int32)
+    sq = np.zeros((net.n, reps), np.int64)
+    sc = np.zeros((net.n + len(w.src), reps), np.float32)
+    check(F["eq_sim_run_scores"](net.h, C.byref(d), None, ptr(st), None, ptr(sq), ptr(sc), ptr(sc[net.n:]), None))
+    g, se = np.zeros(sc.shape[0]), np.zeros(sc.shape[0])
+    check(F["eq_grad_reduce_reach"](net.h, reps, K, ptr(hold), ptr(sq), ptr(sc), ptr(g), ptr(se), None))
+    rg, rse = oracle.lr_gradient_reach(sq.T, hold, K, sc.T, oracle.reach_sets(w))
+    assert np.allclose(g, rg, rtol=1e-10, atol=1e-9 * np.abs(rg).max())
+    assert np.allclose(se, rse, rtol=1e-6, atol=1e-9 * rse.max())
 
 
 def case_batch():

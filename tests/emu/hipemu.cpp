@@ -227,8 +227,8 @@ int worker_count() {
 }
 
 void execute(dim3 grid, dim3 block, size_t shmem, const std::function<void()> &body) {
-  if (grid.y != 1 || grid.z != 1) fatal("only one-dimensional grids are emulated");
-  const long long blocks = grid.x;
+  if (grid.z != 1) fatal("only one- and two-dimensional grids are emulated");
+  const long long blocks = (long long)grid.x * grid.y;
   if (blocks <= 0) return;
   const int nw = (int)std::min<long long>(worker_count(), blocks);
   {
@@ -242,7 +242,7 @@ void execute(dim3 grid, dim3 block, size_t shmem, const std::function<void()> &b
     for (;;) {
       const long long b = next.fetch_add(1);
       if (b >= blocks) break;
-      w->bidx = dim3((unsigned)b);
+      w->bidx = dim3((unsigned)(b % grid.x), (unsigned)(b / grid.x));
       w->bdim = block;
       w->gdim = grid;
       w->lds = shmem ? std::malloc(shmem) : nullptr;

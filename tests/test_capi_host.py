@@ -253,3 +253,17 @@ def test_batch_rejects_repeated_network(eb):
     h = C.c_void_p()
     assert eb.eq_batch_create(2, arr, C.byref(h)) == 0 and h.value
     eb.eq_batch_destroy(h)
+
+
+from hypothesis import given, settings  # noqa: E402
+
+from net_strategies import random_networks  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None)
+@given(random_networks())
+def test_reach_table_equals_the_oracle(net):
+    """The library's reach table (rows: mu of every station, then lambda0 of every source) is the
+    oracle's on random networks, feedback, self-loops and duplicate entries included."""
+    from paper_2402_13259_amd import binding as eb
+    assert np.array_equal(eb.Net(net).reach(), oracle.reach_sets(net))

@@ -187,3 +187,117 @@ def test_gradient_matches_crn_finite_differences(scheme):
         diff = (fs[0][0] - fs[1][0]) / (fs[0][1] - fs[1][1])
         fd, fd_se = diff.mean(), diff.std() / math.sqrt(R)
         assert abs(g[j] - fd) < 4 * math.hypot(se[j], fd_se), (name, i, g[j], se[j], fd, fd_se)
+
+
+# ---------------------------------------------------------------------------------------------
+# Reachability-pruned estimator: parameter j's score is correlated only with the cost of the
+# stations that parameter j can reach (its station and everything downstream).  Pinned on the
+# exact law of a two-station tandem, where the downstream station's cost depends on the upstream
+# service rate (a pruning that drops it is biased) and the upstream cost does not depend on
+# the downstream rate (keeping it only adds variance).
+def tandem_exact_cost(lam, mu0, mu1, c0, c1, p, h, K, hold, nmax=40):
+    """(1/K) sum_{tau=1..K} E[sum_i hold_i (N_tau,i - c_i)^+] for the backward scheme of the
+    tandem 0 -> 1 (routing probability p, exit 1 - p; station 1 exits), from empty, by
+    propagating the exact joint law of (N_0, N_1) (mass beyond nmax kept at nmax)."""
+    N = nmax + 1
+    arr = st.poisson.pmf(np.arange(N), lam * h)
+    shift = np.zeros((N, N))                      # shift[y, x'] = P(y + A = x')
+    for y in range(N):
+        shift[y, y:] = arr[:N - y]
+        shift[y, N - 1] += 1.0 - arr[:N - y].sum()
+    U = np.zeros((N, N, N))                       # U[x0, r, x0'] = sum_d0 P(d0|x0) Bin(r; d0, p) shift[x0-d0, x0']
+    for x0 in range(N):
+        law = death_law(x0, c0, mu0, h)
+        for d0 in range(x0 + 1):
+            U[x0, :d0 + 1, :] += law[d0] * st.binom.pmf(np.arange(d0 + 1), d0, p)[:, None] * shift[x0 - d0][None, :]
+    M1 = np.zeros((N, N, N))                      # M1[r, x1, x1'] = P(x1 - D1 + r = x1')
+    for x1 in range(N):
+        law = death_law(x1, c1, mu1, h)
+        for d1 in range(x1 + 1):
+            for r in range(N):
+                M1[r, x1, min(x1 - d1 + r, N - 1)] += law[d1]
+    P = np.zeros((N, N))
+    P[0, 0] = 1.0
+    q0 = hold[0] * np.maximum(np.arange(N) - c0, 0)
+    q1 = hold[1] * np.maximum(np.arange(N) - c1, 0)
+    tot = 0.0
+    for _ in range(K):
+        V = np.einsum("ab,rbc->arc", P, M1)
+        P = np.einsum("arx,ary->xy", U, V)
+        tot += q0 @ P.sum(1) + q1 @ P.sum(0)
+    return tot / K
+
+
+TANDEM2 = dict(lam=3.0, mu0=2.0, mu1=1.5, c0=2, c1=2, p=0.8, h=0.25, K=24, hold=(4.0, 1.0))
+
+
+def tandem2_net():
+    t = TANDEM2
+    return netgen.tandem(2, p=t["p"], lam=t["lam"]).replace(mu=np.array([t["mu0"], t["mu1"]], np.float32),
+                                                            servers=np.array([t["c0"], t["c1"]], np.int32))
+
+
+@pytest.fixture(scope="module")
+def tandem2_exact_and_sample():
+    t = TANDEM2
+    net = tandem2_net()
+    l32, m0, m1, p32, h32 = (float(np.float32(v)) for v in (t["lam"], t["mu0"], t["mu1"], t["p"], t["h"]))
+    q = float(net.prob[0])
+
+    def J(lam=l32, mu0=m0, mu1=m1):
+        return tandem_exact_cost(lam, mu0, mu1, t["c0"], t["c1"], q, h32, t["K"], t["hold"])
+
+    exact = np.array([d_dtheta(lambda v: J(mu0=v), m0), d_dtheta(lambda v: J(mu1=v), m1),
+                      d_dtheta(lambda v: J(lam=v), l32)])
+    R = 200_000
+    res = oracle.run(net, oracle.BACKWARD, t["h"], t["K"], 515, np.arange(R), scores=True)
+    S = np.concatenate([res["score_mu"], res["score_lam"]], axis=1)
+    return {"net": net, "J": J(), "exact": exact, "res": res, "S": S, "R": R}
+
+
+def test_tandem2_exact_cost_matches_the_oracle(tandem2_exact_and_sample):
+    t, d = TANDEM2, tandem2_exact_and_sample
+    f = oracle.cost_per_rep(d["res"]["sumQ"], np.array(t["hold"]), t["K"])
+    assert d["J"] > 0.3
+    assert abs(f.mean() - d["J"]) < 4.5 * f.std() / math.sqrt(d["R"])
+
+
+def test_reach_sets_of_the_tandem():
+    reach = oracle.reach_sets(tandem2_net())
+    assert reach.tolist() == [[True, True], [False, True], [True, True]]
+
+
+def test_pruned_gradient_matches_exact_chain(tandem2_exact_and_sample):
+    t, d = TANDEM2, tandem2_exact_and_sample
+    hold = np.array(t["hold"])
+    reach = oracle.reach_sets(d["net"])
+    g, se = oracle.lr_gradient_reach(d["res"]["sumQ"], hold, t["K"], d["S"], reach)
+    ex = d["exact"]
+    assert ex[0] < 0 and ex[1] < 0 < ex[2]
+    assert np.all(np.abs(g - ex) < 4 * se), (g, ex, se)
+    assert np.all(se < 0.2 * np.abs(ex)), (se, ex)                      # the check has power
+    # against the full-cost estimator: the same expectation, less variance where pruning applies
+    gf, sef = oracle.lr_gradient(oracle.cost_per_rep(d["res"]["sumQ"], hold, t["K"]), d["S"])
+    assert np.all(np.abs(gf - ex) < 4 * sef)
+    assert se[1] < 0.5 * sef[1] and np.allclose(se[[0, 2]], sef[[0, 2]])
+
+
+@pytest.mark.parametrize("mistake", ["ancestors", "without_self", "self_only"])
+def test_planted_reach_mistakes_fail(tandem2_exact_and_sample, mistake):
+    """A wrong reach set (ancestors in place of descendants, the parameter's own station left
+    out, or only its own station) makes the estimate miss the exact derivative."""
+    t, d = TANDEM2, tandem2_exact_and_sample
+    n = d["net"].n
+    reach = oracle.reach_sets(d["net"])
+    if mistake == "ancestors":
+        wrong = np.concatenate([reach[:n].T, reach[n:]], axis=0)
+    elif mistake == "without_self":
+        wrong = reach.copy()
+        wrong[np.arange(n), np.arange(n)] = False
+        wrong[n, 0] = False
+    else:
+        wrong = np.zeros_like(reach)
+        wrong[np.arange(n), np.arange(n)] = True
+        wrong[n, 0] = True
+    g, se = oracle.lr_gradient_reach(d["res"]["sumQ"], np.array(t["hold"]), t["K"], d["S"], wrong)
+    assert np.any(np.abs(g - d["exact"]) > 4 * se), (g, d["exact"], se)   # the pin's own threshold
