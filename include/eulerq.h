@@ -169,6 +169,21 @@ size_t eq_sim_workspace_bytes(const eq_net *net, const eq_run_desc *desc);
 int eq_sim_run(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t *d_state,
                int64_t *d_sums, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): eq_sim_run with the same arguments, results and
+ * stream semantics, making no allocation.  The SWEEP kernel's inflow slots live in a static
+ * device array of EQ_NOALLOC_SCRATCH_BYTES (64 MiB) that each device holds from the library's
+ * first call on it until the process ends; a run needing more (2 n reps int32 for the
+ * backward scheme, sum_j D_j reps int32 for the forward scheme; see eq_sim_workspace_bytes)
+ * returns EQ_EINVAL.  The TILE kernel needs no scratch.  The network's device tables must
+ * already exist for this device, dt and n_steps (one eq_sim_run with the same dt and n_steps
+ * builds them), else EQ_EINVAL.  Every call on a device shares that device's array and keeps
+ * what the last call left there (each run clears its slots first): calls that overlap on one
+ * device, on any streams, race. */
+#define EQ_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int eq_sim_run_noalloc(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t *d_state,
+                       int64_t *d_sums, void *stream);
+
 /* The scheme of eq_sim_run (Section 2.2, Algorithms 1-2; Algorithm 3 departures) with the
  * statistics of eq_stats_reduce, as one synchronous call on host buffers.  It allocates the
  * device buffers, runs (eq_sim_run on the default stream), reduces the statistics

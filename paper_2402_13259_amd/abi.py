@@ -13,7 +13,7 @@ EQ_KERNEL_AUTO, EQ_KERNEL_TILE, EQ_KERNEL_SWEEP = 0, 1, 2
 TILE_REPS = 64
 
 EXPORTS = ["eq_net_create", "eq_net_destroy", "eq_net_set_staffing", "eq_net_set_params", "eq_sim_run_host", "eq_net_tables", "eq_net_levels", "eq_sim_workspace_bytes",
-           "eq_sim_run", "eq_sim_tune", "eq_sim_run_pair", "eq_stats_reduce", "eq_stats_reduce_pair",
+           "eq_sim_run", "eq_sim_run_noalloc", "eq_sim_tune", "eq_sim_run_pair", "eq_stats_reduce", "eq_stats_reduce_pair",
            "eq_sim_run_record", "eq_sojourn", "eq_sim_check", "eq_batch_create", "eq_batch_destroy",
            "eq_batch_layout", "eq_batch_run", "eq_batch_tune", "eq_batch_check", "eq_sim_run_scores", "eq_cost_reduce",
            "eq_grad_reduce", "eq_grad_reduce_reach", "eq_net_reach", "eq_selftest_math", "eq_selftest_sample", "eq_selftest_score", "eq_selftest_valu_peak", "eq_selftest_philox",
@@ -52,6 +52,7 @@ _sig = {
     "eq_net_levels": ([_vp, _vp], C.c_int),
     "eq_sim_workspace_bytes": ([_vp, C.POINTER(eq_run_desc)], C.c_size_t),
     "eq_sim_run": ([_vp, C.POINTER(eq_run_desc), _vp, _vp, _vp, _vp], C.c_int),
+    "eq_sim_run_noalloc": ([_vp, C.POINTER(eq_run_desc), _vp, _vp, _vp, _vp], C.c_int),
     "eq_sim_tune": ([_vp, C.POINTER(eq_run_desc), _i32, _vp, _vp, C.POINTER(eq_run_desc)], C.c_int),
     "eq_stats_reduce": ([_vp, C.POINTER(eq_run_desc), _vp, _vp, _vp, _vp, _vp], C.c_int),
     "eq_sim_run_pair": ([_vp, C.POINTER(eq_run_desc), _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),

@@ -71,6 +71,8 @@ int ensure_device(int *dev_out) {
     sampler_tables(rcp, fc);
     e = eq::upload_sampler_tables(rcp, fc);
     if (e != hipSuccess) return hip_fail(e, "upload sampler tables");
+    e = eq::setup_noalloc_scratch(dev);
+    if (e != hipSuccess) return hip_fail(e, "address of the allocation-free scratch");
     g_dev_ready[dev] = true;
   }
   *dev_out = dev;
@@ -748,8 +750,10 @@ struct RecBufs {
   int32_t *N, *D, *R;
 };
 
+// scratch: inflow slots of the sweep kernels supplied by the caller (the allocation-free entry
+// point), big enough for the run; nullptr: the network's own workspace, grown as needed.
 int run_sim(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t *d_state, int64_t *d_sums,
-            const ScoreBufs *sc, hipStream_t st, const RecBufs *rec = nullptr) {
+            const ScoreBufs *sc, hipStream_t st, const RecBufs *rec = nullptr, int *scratch = nullptr) {
   int rc = check_desc(net, desc);
   if (rc) return rc;
   if (!d_state) return fail(EQ_EINVAL, "d_state is null");
@@ -787,7 +791,7 @@ int run_sim(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t
   }
   // sweep kernel: workspace of inflow slots
   const size_t ws = (size_t)(ring_slots(*net, desc->scheme) * desc->reps) * sizeof(int32_t);
-  if (ws > net->ws_cap) {
+  if (!scratch && ws > net->ws_cap) {
     // runs queued earlier on any stream may still use the old workspace
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     (void)hipFree(net->d_ws);
@@ -799,7 +803,8 @@ int run_sim(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t
   }
   eq::SweepArgs a;
   std::memset(&a, 0, sizeof a);
-  a.v = make_view(*net, *desc, d_state, net->d_ws, reinterpret_cast<long long *>(d_sums));
+  int *const ring = scratch ? scratch : net->d_ws;
+  a.v = make_view(*net, *desc, d_state, ring, reinterpret_cast<long long *>(d_sums));
   if (sc) {
     const long long per = (long long)net->n * desc->reps;
     a.v.scp = net->d_scp;
@@ -827,7 +832,7 @@ int run_sim(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t
   a.flags = net->d_flags;
   a.dep_mode = desc->dep_mode;
   a.dt = desc->dt;
-  if ((e = eq::launch_sweep_init(d_state, d_init, (long long)net->n * desc->reps, net->d_ws,
+  if ((e = eq::launch_sweep_init(d_state, d_init, (long long)net->n * desc->reps, ring,
                                  (long long)(ws / sizeof(int32_t)), a.v.tsums, d_sums ? nsums : 0, st)) != hipSuccess)
     return hip_fail(e, "init launch");
   const int iters = desc->n_steps > 0 ? desc->n_steps + a.v.extra : 0;
@@ -849,6 +854,31 @@ extern "C" {
 int eq_sim_run(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t *d_state,
                int64_t *d_sums, void *stream) {
   return run_sim(net, desc, d_init, d_state, d_sums, nullptr, (hipStream_t)stream);
+}
+
+static_assert(EQ_NOALLOC_SCRATCH_BYTES == eq::kNoAllocScratchBytes, "scratch size of the header and the kernels");
+
+int eq_sim_run_noalloc(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t *d_state,
+                       int64_t *d_sums, void *stream) {
+  int rc = check_desc(net, desc);
+  if (rc) return rc;
+  if (!d_state) return fail(EQ_EINVAL, "d_state is null");
+  if (d_init && d_init == d_state) return fail(EQ_EINVAL, "d_init must not alias d_state");
+  int dev = 0;
+  if ((rc = ensure_device(&dev))) return rc;
+  // building the device tables allocates: they must already hold this run's (h, K)
+  if (net->device != dev || !net->dev_valid || net->dev_dt != desc->dt || net->dev_K != desc->n_steps)
+    return fail(EQ_EINVAL, "the network's device tables are not built for this device, h and n_steps "
+                           "(one eq_sim_run with the same h and n_steps builds them)");
+  int *scratch = eq::noalloc_scratch(dev);
+  if (!scratch) return fail(EQ_EDEVICE, "the allocation-free scratch is not set up on device %d", dev);
+  if (pick_kernel(*net, *desc) == EQ_KERNEL_SWEEP) {
+    const long long need = (long long)ring_slots(*net, desc->scheme) * desc->reps * (long long)sizeof(int32_t);
+    if (need > eq::kNoAllocScratchBytes)
+      return fail(EQ_EINVAL, "this run needs %lld bytes of scratch; the allocation-free entry point has %lld",
+                  need, eq::kNoAllocScratchBytes);
+  }
+  return run_sim(net, desc, d_init, d_state, d_sums, nullptr, (hipStream_t)stream, nullptr, scratch);
 }
 
 int eq_sim_run_host(eq_net *net, const eq_run_desc *desc, const int32_t *init, int32_t *final_state,

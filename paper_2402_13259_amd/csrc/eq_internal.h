@@ -159,6 +159,13 @@ hipError_t launch_sojourn(const SojournArgs &a, hipStream_t st);
 hipError_t launch_batch_step(const BatchArgs &a, long long tasks, int scheme, int waves_per_block, hipStream_t st);
 hipError_t launch_batch_finish(const BatchArgs &a, long long tasks, int waves_per_block, hipStream_t st);
 hipError_t upload_sampler_tables(const float *rcp, const float *fc);
+
+// Scratch of the allocation-free run entry point: a static device array of this many bytes
+// (the sweep kernels' inflow slots).  setup_noalloc_scratch takes its address on device `dev`
+// (current) once; noalloc_scratch returns it (nullptr before set-up).
+constexpr long long kNoAllocScratchBytes = 64ll << 20;
+hipError_t setup_noalloc_scratch(int dev);
+int *noalloc_scratch(int dev);
 hipError_t launch_backward(const SimArgs &a, int grid, int block, size_t lds, hipStream_t st);
 hipError_t launch_forward(const SimArgs &a, int grid, int block, size_t lds, hipStream_t st);
 hipError_t launch_stats(const long long *tsums, const int *state, const long long *tsums2,

@@ -424,3 +424,25 @@ hipError_t launch_selftest_philox(long long count, const uint32_t *ctr, const ui
 
 // The sweep kernels share this translation unit (and its __constant__ sampler tables).
 #include "eq_sweep.h"
+
+namespace eq {
+
+// The inflow slots of eq_sim_run_noalloc's sweep kernels live here instead of in a workspace
+// the library allocates.  Each device holds its own copy; host code uses only the address that
+// hipGetSymbolAddress returns for it on that device, never the name.
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) int scratch[kNoAllocScratchBytes / sizeof(int)];
+static int *g_scratch_ptr[kScratchDevices];
+
+hipError_t setup_noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = static_cast<int *>(p);
+  return hipSuccess;
+}
+
+int *noalloc_scratch(int dev) { return dev >= 0 && dev < kScratchDevices ? g_scratch_ptr[dev] : nullptr; }
+
+}  // namespace eq

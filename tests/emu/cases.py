@@ -250,7 +250,39 @@ def case_oracle(lib_path: str):
             assert np.array_equal(a, b)
 
 
-CASES = {"record_sojourn": case_record_sojourn, "kernels": case_kernels, "scores": case_scores, "batch": case_batch,
+def case_noalloc():
+    """eq_sim_run_noalloc: refused before the network's tables exist, then equal to eq_sim_run on
+    two calls in a row (the second with fewer replications and the other scheme), with the tile
+    kernel too; a run needing more scratch than the static array is refused."""
+    w = netgen.config2().net
+    net = Net(w)
+    h, K = 0.01, 120
+
+    def noalloc(d):
+        st = np.zeros((net.n, d.reps), np.int32)
+        sums = np.zeros((3, net.n, tiles(d.reps)), np.int64)
+        rc = F["eq_sim_run_noalloc"](net.h, C.byref(d), None, ptr(st), ptr(sums), None)
+        return rc, st, sums
+
+    d1 = desc(0, h, K, 200, 8, abi.EQ_KERNEL_SWEEP)
+    rc, _, _ = noalloc(d1)
+    assert rc == abi.EQ_EINVAL and b"tables" in F["eq_last_error"]()
+    for d in (d1, desc(1, h, K, 70, 8, abi.EQ_KERNEL_SWEEP), desc(1, h, K, 70, 8, abi.EQ_KERNEL_TILE)):
+        st, sums = run(net, d)
+        rc, st2, sums2 = noalloc(d)
+        assert rc == 0, F["eq_last_error"]()
+        assert np.array_equal(st, st2) and np.array_equal(sums, sums2), (d.scheme, d.reps, d.kernel)
+        assert_run_equals_oracle(w, d.scheme, h, K, d.reps, 8, st2, sums2)
+    big = netgen.config3().net
+    nb = Net(big)
+    run(nb, desc(1, 0.005, 1, 1, 0, abi.EQ_KERNEL_TILE))
+    d = desc(1, 0.005, 1, 4096, 0, abi.EQ_KERNEL_SWEEP)
+    st = np.zeros((nb.n, 4096), np.int32)
+    assert F["eq_sim_run_noalloc"](nb.h, C.byref(d), None, ptr(st), None, None) == abi.EQ_EINVAL
+    assert b"bytes of scratch" in F["eq_last_error"]()
+
+
+CASES = {"noalloc": case_noalloc, "record_sojourn": case_record_sojourn, "kernels": case_kernels, "scores": case_scores, "batch": case_batch,
          "oracle": case_oracle}
 
 if __name__ == "__main__":

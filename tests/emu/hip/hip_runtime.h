@@ -28,6 +28,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __constant__
+#define __align__(n) __attribute__((aligned(n)))
 // a workgroup runs on one host thread, so a thread-local static is shared by exactly its
 // GPU threads (and, like LDS, holds stale contents when the next workgroup starts)
 #define __shared__ static thread_local

@@ -65,3 +65,7 @@ def test_oracle_sanitized(emu_env, tmp_path):
                                extra_flags=["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                                             "-fno-sanitize-recover=all"])
     run_case(emu_env, "oracle", lib)
+
+
+def test_allocation_free_entry_point_sanitized(emu_env):
+    run_case(emu_env, "noalloc")
