@@ -15,14 +15,14 @@ ride along (--main-only leaves them out):
   host_buffers    the main workload's backward scheme through the host-buffer entry point
                   (allocation and PCIe copies included);
   sojourn         recording runs and sojourn-time sampling on a 100-station Jackson network;
-  paper_table1_shape  each scheme on a 1000-station, 200-server stand-in of the paper's Table 1
-                  network, beside the paper's own per-replication CPU rates (context only);
   batching        512 feed-forward networks of 10..2000 stations (T ~ U(10, 100), h = 0.01, 256
                   replications each, backward scheme) in one autotuned, graph-captured batch,
-                  against one autotuned run per network on a sample of every 16th network;
+                  against one autotuned run per network, every network one after another;
   gradient        the likelihood-ratio gradient of the expected waiting-plus-staffing cost of the
                   1000-station DAG (8192 replications, full horizon, backward scheme): score run
-                  plus fp64 reductions, against the plain run of the same simulation.
+                  plus fp64 reductions (the reachability-pruned estimator the autograd function
+                  uses), against the plain run of the same simulation; the full-cost estimator's
+                  standard errors beside it.
 """
 import argparse
 import json
@@ -33,14 +33,20 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Counter-derived figures of the sweep kernel on this workload (rocprofv3 summaries in
-# profiles/), valid for the kernel sources whose hash is recorded:
-#   ops   = active VALU lane-operations per station-step
-#           = SQ_INSTS_VALU * 64 * SQ_THREAD_CYCLES_VALU / (SQ_ACTIVE_INST_VALU * 64) / station-steps
-#   bytes = HBM bytes per station-step = (2.0 * FETCH_SIZE + 1.0 * WRITE_SIZE) / station-steps,
-#           the factors from a plain 1 GiB device copy measured with the same counters.
-KERNEL_COUNTERS = {"sources_sha256_16": "fd660d14313f7fd6", "ops_per_station_step": 972.0,
-                   "traffic_bytes_per_station_step": 37.43}
+# Counter-derived figures of the sweep kernel on this workload over the benchmark step's full
+# horizon (rocprofv3 summaries in profiles/), valid for the kernel sources whose hash is recorded:
+#   active = active VALU lane-operations per station-step
+#          = SQ_INSTS_VALU * 64 * SQ_THREAD_CYCLES_VALU / (SQ_ACTIVE_INST_VALU * 64) / station-steps
+#   slots  = issued VALU lane slots per station-step = SQ_INSTS_VALU * 64 / station-steps
+#   bytes  = HBM bytes per station-step = (2.0 * FETCH_SIZE + 1.0 * WRITE_SIZE) / station-steps,
+#            the factors from a plain 1 GiB device copy measured with the same counters.
+KERNEL_COUNTERS = {"sources_sha256_16": "unmeasured", "active_lane_ops_per_station_step": None,
+                   "issued_lane_slots_per_station_step": None, "traffic_bytes_per_station_step": None}
+# The algorithm's own operations per station-step: the oracle's event counts on this workload
+# (tests/golden/op_counts_dag1000.json) priced with the VALU instruction counts of each sampler
+# building block in the gfx950 build (tests/isa/op_costs_gfx950.json).
+OP_COUNTS_JSON = os.path.join(ROOT, "tests", "golden", "op_counts_dag1000.json")
+OP_COSTS_JSON = os.path.join(ROOT, "tests", "isa", "op_costs_gfx950.json")
 KERNEL_SOURCES = ["paper_2402_13259_amd/csrc/eq_device.h", "paper_2402_13259_amd/csrc/eq_internal.h",
                   "paper_2402_13259_amd/csrc/eq_sweep.h", "paper_2402_13259_amd/csrc/eq_kernels.hip"]
 # VALU peak for the kernel's (non-packed) instructions: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -48,6 +54,39 @@ KERNEL_SOURCES = ["paper_2402_13259_amd/csrc/eq_device.h", "paper_2402_13259_amd
 # x 2 for packed fp32 x 2 for an FMA; the kernels are built without packed fp32.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_ops() -> float:
+    """Operations per station-step of the benchmark step (the mean of its two schemes)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "isa"))
+    import op_costs
+    costs = json.load(open(OP_COSTS_JSON))["events"]
+    counts = json.load(open(OP_COUNTS_JSON))
+    return 0.5 * sum(op_costs.algorithmic_ops(counts[s], costs) for s in ("backward", "forward"))
+
+
+def summarize_counters(path: str, regex: str) -> None:
+    """Sum every counter of rocprofv3's counter_collection CSV files under `path` over the
+    dispatches of kernels matching `regex`; print the sums and the dispatch count as JSON."""
+    import csv
+    import glob
+    import re
+    sums, dispatches, per_kernel = {}, set(), {}
+    pat = re.compile(regex)
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if not pat.search(row["Kernel_Name"]):
+                    continue
+                dispatches.add(row["Dispatch_Id"])
+                name, v = row["Counter_Name"], float(row["Counter_Value"])
+                sums[name] = sums.get(name, 0.0) + v
+                k = per_kernel.setdefault(row["Kernel_Name"][:80], {"dispatches": set(), "sums": {}})
+                k["dispatches"].add(row["Dispatch_Id"])
+                k["sums"][name] = k["sums"].get(name, 0.0) + v
+    per_kernel = {k: {"dispatches": len(v["dispatches"]), "sums": v["sums"]} for k, v in per_kernel.items()}
+    print(json.dumps({"path": path, "kernels": regex, "dispatches": len(dispatches), "sums": sums,
+                      "per_kernel": per_kernel}), flush=True)
 
 
 def sources_hash() -> str:
@@ -73,13 +112,14 @@ def parse():
     ap.add_argument("--main-only", action="store_true",
                     help="only the main step and its roofline (no average-scheme, staffing, sojourn, batching "
                          "or gradient legs): the form the kernel profiles are taken with")
-    ap.add_argument("--per-net-stride", type=int, default=16, help="per-network baseline: every k-th network")
+    ap.add_argument("--per-net-stride", type=int, default=1,
+                    help="per-network baseline: every k-th network (1: all of them)")
     ap.add_argument("--error-order", action="store_true",
                     help="run only the error-order study of the backward, forward and average schemes")
-    ap.add_argument("--server-scaling", action="store_true",
-                    help="run only the average scheme's throughput against the server count (the paper's Table 2 shape)")
     ap.add_argument("--fd-check", action="store_true",
                     help="run only the finite-difference check of the gradient at full size (several minutes)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("DIR", "KERNEL_REGEX"),
+                    help="sum rocprofv3 counter CSVs under DIR over the kernels matching KERNEL_REGEX (no GPU)")
     return ap.parse_args()
 
 
@@ -97,6 +137,9 @@ def copy_calibration(mb: int) -> None:
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: replications shard across GPUs by design (every draw is keyed "
               "by the global replication id), but this benchmark runs and reports a single MI355X only",
@@ -110,9 +153,6 @@ def main():
         return
     if args.error_order:
         error_order()
-        return
-    if args.server_scaling:
-        server_scaling()
         return
     import numpy as np
     import torch
@@ -170,18 +210,27 @@ def main():
             "avg_launch_ms": round(per_launch_ms, 5),
             "station_steps_per_launch": ss_per_launch}
     roof["measured_fma_peak"] = round(eb.valu_peak() / 1e12, 2)   # non-packed fp32 FMA lanes, T/s
-    current = sources_hash() == KERNEL_COUNTERS["sources_sha256_16"]
-    if current:
-        ops = KERNEL_COUNTERS["ops_per_station_step"]
-        achieved = ops * ss_per_launch / (per_launch_ms * 1e-3) / 1e12
+    launch_s = per_launch_ms * 1e-3
+    alg = algorithmic_ops()
+    achieved = alg * ss_per_launch / launch_s / 1e12
+    roof.update(achieved=round(achieved, 3), frac=round(achieved / VALU_PEAK_TOPS, 4),
+                ops_per_station_step=round(alg, 1),
+                ops_basis="the algorithm's operations: oracle event counts on this workload (Philox blocks, "
+                          "uniforms, sampler set-ups, search steps, rejection attempts, routed edges) x VALU "
+                          "instructions of each building block in the gfx950 build")
+    if sources_hash() == KERNEL_COUNTERS["sources_sha256_16"]:
+        act = KERNEL_COUNTERS["active_lane_ops_per_station_step"]
+        slots = KERNEL_COUNTERS["issued_lane_slots_per_station_step"]
         traffic = KERNEL_COUNTERS["traffic_bytes_per_station_step"] * ss_per_launch
-        roof.update(achieved=round(achieved, 3), frac=round(achieved / VALU_PEAK_TOPS, 4),
-                    ops_per_station_step=ops, traffic=round(traffic),
-                    hbm_gbs=round(traffic / (per_launch_ms * 1e-3) / 1e9, 1),
-                    hbm_frac=round(traffic / (per_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+        roof["executed"] = {"active_lane_ops_per_station_step": act, "issued_lane_slots_per_station_step": slots,
+                            "lane_utilisation": round(act / slots, 4),
+                            "algorithmic_share_of_active": round(alg / act, 4),
+                            "frac": round(act * ss_per_launch / launch_s / 1e12 / VALU_PEAK_TOPS, 4)}
+        roof.update(traffic=round(traffic), hbm_gbs=round(traffic / launch_s / 1e9, 1),
+                    hbm_frac=round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4))
     else:
         # counters were taken on other kernel sources: re-profile before quoting them
-        roof.update(achieved=None, frac=None, traffic=None, note="kernel changed since counters were taken")
+        roof.update(executed=None, traffic=None, note="kernel changed since the counters were taken")
 
     out = {
         "metric": "Euler station-steps/s at 1 GPU; batched vs per-net launch; grad/fwd time",
@@ -192,7 +241,7 @@ def main():
                                "load U(0.85,0.99), h=0.005, T=100 (20000 steps), 4096 replications, "
                                "backward + forward schemes + statistics per step",
                    "n": n, "K": K, "reps": reps, "schemes": ["backward", "forward"],
-                   "kernel": "sweep"},
+                   "kernel": "sweep", "network_sha256": w.net.fingerprint()},
         "per_scheme_station_steps_per_s": {"backward": n * K * reps / (sweep_ms[0] * 1e-3),
                                            "forward": n * K * reps / (sweep_ms[1] * 1e-3)},
         "roofline": roof,
@@ -204,7 +253,6 @@ def main():
         out["staffing"] = bench_staffing(w, K, sweep_ms)
         out["host_buffers"] = bench_host_buffers(w, K, sweep_ms)
         out["sojourn"] = bench_sojourn()
-        out["paper_table1_shape"] = bench_paper_shape()
     if not (args.skip_batch or args.main_only):
         out["batching"] = bench_batching(args.per_net_stride)
     if not (args.skip_grad or args.main_only):
@@ -253,7 +301,7 @@ def bench_batching(stride: int) -> dict:
     batched = ss_all / batch_s
     # per network: every `stride`-th network, its own autotuned launch shape, one after another
     sample = list(range(0, len(ws), stride))
-    shapes = [eb.tune(nets[k], eb.EQ_BACKWARD, dt, ks[k], reps, 0, trial_steps=64) for k in sample]
+    shapes = [eb.tune(nets[k], eb.EQ_BACKWARD, dt, ks[k], reps, 0, trial_steps=32) for k in sample]
     bufs = [(torch.empty((nets[k].n, reps), dtype=torch.int32, device="cuda"),
              torch.empty((3, nets[k].n, eb.n_tiles(reps)), dtype=torch.int64, device="cuda")) for k in sample]
     torch.cuda.synchronize()
@@ -275,7 +323,17 @@ def bench_batching(stride: int) -> dict:
             "per_network_sample": f"networks {sample[0]}, {sample[0] + stride}, ..., {sample[-1]} ({len(sample)}), "
                                   f"full horizons, {ss_sample:.3g} station-steps, {per_s:.2f} s, each with its "
                                   f"autotuned shape ({kinds['tile']} tile, {kinds['sweep']} sweep)",
+            "per_network_s": round(per_s, 3), "networks_sha256": batch_fingerprint(ws),
             "batched_over_per_network": batched / per_net}
+
+
+def batch_fingerprint(ws) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for w in ws:
+        h.update(w.net.fingerprint().encode())
+        h.update(repr((w.T, w.dt, w.reps, w.net_id)).encode())
+    return h.hexdigest()
 
 
 def bench_gradient() -> dict:
@@ -301,8 +359,8 @@ def bench_gradient() -> dict:
     def scored():
         r = eb.simulate_scores(net, eb.EQ_BACKWARD, w.dt, K, R, 0, state=state, sumq=sumq, score=score, check=False)
         f, ms = eb.cost_reduce(hold_d, r.sumq, K)
-        g, se = eb.grad_reduce(f, ms, r.score)
-        return ms, g, se
+        g, se = eb.grad_reduce_reach(net, hold_d, r.sumq, r.score, K)
+        return ms, g, se, f
 
     # short warm-up of both paths (kernels loaded, tables for this horizon uploaded)
     eb.simulate(net, eb.EQ_BACKWARD, w.dt, K, R, 0, state=state, with_sums=False, kernel=eb.EQ_KERNEL_SWEEP)
@@ -317,16 +375,35 @@ def bench_gradient() -> dict:
         times[name] = e0.elapsed_time(e1)
     if eb.eq_sim_check(net.handle, stream.cuda_stream) != 0:
         raise SystemExit(f"gradient run device flags: {eb.eq_last_error().decode()}")
-    ms, g, se = out
-    ms, g, se = ms.cpu().numpy(), g.cpu().numpy(), se.cpu().numpy()
+    ms_d, g, se, f = out
+    e0, e1 = _events()
+    e0.record(stream)
+    gf, sef = eb.grad_reduce(f, ms_d, score)
+    e1.record(stream)
+    gr0, gr1 = _events()
+    gr0.record(stream)
+    eb.grad_reduce_reach(net, hold_d, sumq, score, K)
+    gr1.record(stream)
+    torch.cuda.synchronize()
+    full_ms, reach_ms = e0.elapsed_time(e1), gr0.elapsed_time(gr1)
+    ms, g, se, gf, sef = (x.cpu().numpy() for x in (ms_d, g, se, gf, sef))
     staffing = float(np.dot(staff, w.net.servers))
+
+    def med(se_, g_, sel=slice(None)):
+        return float(np.median(se_[sel] / np.maximum(np.abs(g_[sel]), 1e-300)))
     return {"workload": "1000-station DAG, 8192 replications, 20000 steps, backward scheme; cost = sum_i hold_i "
                         "mean (N_i - m_i)^+ + sum_i k_i m_i, hold ~ U(1, 5), k ~ U(0.1, 1); 1000 mu + 50 lambda0",
             "forward_ms": round(times["forward"], 1), "grad_ms": round(times["forward_score_reduce"], 1),
             "grad_over_forward": times["forward_score_reduce"] / times["forward"],
             "J": float(ms[0] + staffing), "J_se": float(ms[1]),
-            "grad_norm": float(np.linalg.norm(g)), "median_grad_se_over_abs": float(np.median(se / np.maximum(
-                np.abs(g), 1e-300)))}
+            "estimator": "each score against the cost of the stations its parameter can reach",
+            "grad_norm": float(np.linalg.norm(g)), "median_grad_se_over_abs": med(se, g),
+            "median_grad_se_over_abs_mu": med(se, g, slice(0, n)),
+            "median_grad_se_over_abs_lambda0": med(se, g, slice(n, None)),
+            "reach_reduce_ms": round(reach_ms, 3), "full_reduce_ms": round(full_ms, 3),
+            "full_cost_estimator": {"median_grad_se_over_abs": med(sef, gf),
+                                    "median_grad_se_over_abs_mu": med(sef, gf, slice(0, n)),
+                                    "median_se_ratio_reach_over_full_mu": float(np.median(se[:n] / sef[:n]))}}
 
 
 def bench_pair(w, K, net, sweep_ms) -> dict:
@@ -470,80 +547,6 @@ def bench_sojourn(samples: int = 64) -> dict:
     return out
 
 
-def bench_paper_shape() -> dict:
-    """Context for the paper's own timings (its Table 1: n = 1000 stations, m = 200 servers,
-    h = 0.01; one replication per run on a 64-core CPU in Python): a synthetic stand-in of that
-    shape (the paper does not give its routing; here the feed-forward Jackson generator with 10
-    layers of 100 stations, 200 servers each), horizon 100, 4096 replications, each scheme and
-    the average scheme's pair run timed with HIP events.  The paper's per-replication rates are
-    derived from its run-times at h = 0.01: backward 1000 * 100000 / 158.1 s, forward / 380.2 s,
-    average 2 * 1000 * 100000 / 386.2 s.  Different machine and network: context only."""
-    import torch
-    import netgen
-    from paper_2402_13259_amd import binding as eb
-    w = netgen.jackson(layers=10, width=100, seed=7, servers=200)
-    h, K, reps = 0.01, 10000, 4096
-    net = eb.Net(w)
-    stream = torch.cuda.current_stream()
-    state = torch.empty((w.n, reps), dtype=torch.int32, device="cuda")
-    sums = torch.empty((3, w.n, eb.n_tiles(reps)), dtype=torch.int64, device="cuda")
-    paper = {"backward": 1000 * 100000 / 158.1, "forward": 1000 * 100000 / 380.2, "average": 2 * 1000 * 100000 / 386.2}
-    out = {"workload": "jackson 10x100 (1000 stations, 200 servers), h=0.01, T=100, 4096 replications; "
-                       "the paper's Table 1 shape, synthetic stand-in"}
-    for name, scheme in (("backward", eb.EQ_BACKWARD), ("forward", eb.EQ_FORWARD), ("average", None)):
-        e0, e1 = _events()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        if scheme is None:
-            eb.simulate_pair(net, h, K, reps, 0, check=False)
-        else:
-            eb.simulate(net, scheme, h, K, reps, 0, state=state, sums=sums, check=False, kernel=eb.EQ_KERNEL_SWEEP)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        ss = (2 if scheme is None else 1) * w.n * K * reps / (ms * 1e-3)
-        out[name] = {"ms": round(ms, 1), "station_steps_per_s": ss,
-                     "paper_cpu_station_steps_per_s_per_replication": round(paper[name]),
-                     "ratio": round(ss / paper[name])}
-    if eb.eq_sim_check(net.handle, stream.cuda_stream) != 0:
-        raise SystemExit(f"paper-shape run device flags: {eb.eq_last_error().decode()}")
-    return out
-
-
-def server_scaling(reps: int = 4096) -> None:
-    """The average scheme's pair run on feed-forward Jackson networks of 100 and 1000 stations
-    (10 layers) with m = 20, 200, 1000 servers per station, h = 0.15, horizon 100 (667 steps):
-    the shape of the paper's Table 2, whose CPU run-time does not change with m.  Here the cost
-    of a station-step grows with the departures a step draws (about rho m mu h), so throughput
-    falls with m.  One JSON line per network, then a summary."""
-    import torch
-    import netgen
-    from paper_2402_13259_amd import binding as eb
-    h, K = 0.15, 667
-    rows = []
-    for width in (10, 100):
-        for m in (20, 200, 1000):
-            w = netgen.jackson(layers=10, width=width, seed=7, servers=m)
-            net = eb.Net(w)
-            eb.simulate_pair(net, h, 20, reps, 1, check=False)           # tables and warm-up
-            torch.cuda.synchronize()
-            e0, e1 = _events()
-            stream = torch.cuda.current_stream()
-            e0.record(stream)
-            eb.simulate_pair(net, h, K, reps, 0, check=False)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            if eb.eq_sim_check(net.handle, stream.cuda_stream) != 0:
-                raise SystemExit(f"server-scaling device flags: {eb.eq_last_error().decode()}")
-            row = {"n": w.n, "m": m, "ms": round(ms, 1), "station_steps_per_s": 2 * w.n * K * reps / (ms * 1e-3),
-                   "mean_departures_per_station_step": round(float(w.total_rates().mean()) * h, 1)}
-            rows.append(row)
-            print(json.dumps(row), flush=True)
-    print(json.dumps({"server_scaling": "jackson, average scheme (pair run), h=0.15, T=100, %d replications" % reps,
-                      "rows": rows}), flush=True)
-
-
 def erlang_c_mean(lam: float, mu: float, c: int) -> float:
     """Steady-state mean number in an M/M/c queue (Erlang B recursion, then Erlang C)."""
     a = lam / mu
@@ -630,11 +633,14 @@ def relative_error_vs_servers(T: float = 1000.0, reps: int = 1024) -> None:
                       "average": [r["average"] for r in rows], "bound": [r["bound"] for r in rows]}), flush=True)
 
 
-def fd_check(rel: float = 0.01) -> None:
+def fd_check(rel: float = 1e-3) -> None:
     """Likelihood-ratio gradient of the 1000-station cost (8192 replications, full horizon,
     backward scheme) against common-random-number central differences: 8 mu coordinates at
-    spread DAG depths, 4 lambda0 coordinates and 4 random directions, each perturbed by
-    +-rel relative to the parameter.  One JSON line per check, then a summary line."""
+    spread DAG depths, 4 lambda0 coordinates and 4 random directions v, each the derivative of
+    J along theta * v with the parameters perturbed by +-rel relative.  The estimate is the
+    reachability-pruned one (each score against the cost of the stations its parameter can
+    reach); the full-cost estimate is reported beside it.  One JSON line per check, then a
+    summary line."""
     import math
     import numpy as np
     import torch
@@ -643,13 +649,19 @@ def fd_check(rel: float = 0.01) -> None:
     w = netgen.config5()
     hold, staff = netgen.config5_costs(w.net.n)
     prob = lr.CostProblem(w.net, hold, staff, w.dt, w.K, w.reps, seed=0)
-    n = w.net.n
+    n, R, K = w.net.n, w.reps, w.K
     net = eb.Net(w.net)
-    res = eb.simulate_scores(net, eb.EQ_BACKWARD, w.dt, w.K, w.reps, 0)
-    f, ms = eb.cost_reduce(torch.as_tensor(hold, device="cuda"), res.sumq, w.K)
-    fc = (f - ms[0]).double()
-    S = res.score.double()
-    R = w.reps
+    res = eb.simulate_scores(net, eb.EQ_BACKWARD, w.dt, K, R, 0)
+    hold_d = torch.as_tensor(hold, device="cuda")
+    f, ms = eb.cost_reduce(hold_d, res.sumq, K)
+    g_reach, _ = eb.grad_reduce_reach(net, hold_d, res.sumq, res.score, K)
+    # per-replication products of both estimators, [R, n_par]
+    S = res.score.double().T
+    reach = torch.as_tensor(net.reach(), dtype=torch.float64, device="cuda")
+    F = (res.sumq.double().T * (hold_d / K)[None, :]) @ reach.T
+    P_reach = (F - F.mean(0)) * S * (R / (R - 1))
+    P_full = (f - ms[0]).double()[:, None] * S * (R / (R - 1))
+    assert torch.allclose(P_reach.mean(0), g_reach, rtol=1e-9, atol=1e-9 * g_reach.abs().max().item())
     theta = np.concatenate([w.net.mu, w.net.lambda0]).astype(np.float64)
     lev = net.levels()
     mus = [int(np.flatnonzero(lev == l)[0]) for l in np.linspace(1, lev.max(), 8).astype(int)]
@@ -657,7 +669,7 @@ def fd_check(rel: float = 0.01) -> None:
     rng = np.random.default_rng(11)
     for d in range(4):
         checks.append(("direction", d, rng.standard_normal(len(theta)) / math.sqrt(len(theta))))
-    zs = []
+    rows = []
     for kind, idx, vec in checks:
         v = np.zeros(len(theta))
         if kind == "mu":
@@ -666,21 +678,28 @@ def fd_check(rel: float = 0.01) -> None:
             v[n + idx] = 1.0
         else:
             v = vec
-        # LR directional derivative along theta * v, per replication, and its SE
-        per = fc * (torch.as_tensor(theta * v, device="cuda")[:, None] * S).sum(0) * R / (R - 1)
-        lr_d, lr_se = per.mean().item(), (per.std() / math.sqrt(R)).item()
+        wv = torch.as_tensor(theta * v, device="cuda")
+        est = {}
+        for name, P in (("lr", P_reach), ("lr_full", P_full)):
+            per = P @ wv
+            est[name] = (per.mean().item(), (per.std() / math.sqrt(R)).item())
         fs = []
         for sign in (+1, -1):
             t = (theta * (1 + sign * rel * v)).astype(np.float32)
             fs.append(lr.cost_samples(prob, mu=t[:n], lambda0=t[n:]))
         diff = ((fs[0] - fs[1]) / (2 * rel)).cpu().numpy()
         fd, fd_se = float(diff.mean()), float(diff.std() / math.sqrt(R))
-        z = (lr_d - fd) / math.hypot(lr_se, fd_se)
-        zs.append(z)
-        print(json.dumps({"check": kind, "index": idx,
-                          "lr": lr_d, "lr_se": lr_se, "fd": fd, "fd_se": fd_se, "z": z}), flush=True)
+        comb = math.hypot(est["lr"][1], fd_se)
+        row = {"check": kind, "index": idx, "lr": est["lr"][0], "lr_se": est["lr"][1], "lr_full": est["lr_full"][0],
+               "lr_full_se": est["lr_full"][1], "fd": fd, "fd_se": fd_se, "z": (est["lr"][0] - fd) / comb,
+               "combined_se_over_abs_fd": comb / abs(fd) if fd else None}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    zs = [r["z"] for r in rows]
     print(json.dumps({"fd_check": "grad1000", "checks": len(zs), "max_abs_z": max(abs(z) for z in zs),
                       "within_3_se": sum(abs(z) < 3 for z in zs), "relative_step": rel,
+                      "with_power": sum(r["combined_se_over_abs_fd"] is not None and r["combined_se_over_abs_fd"] < 0.3
+                                        for r in rows),
                       "units": "derivative of J along theta * v (relative perturbation)"}), flush=True)
 
 
@@ -700,7 +719,16 @@ def cpu_baseline(w, K, seconds):
         oracle.run(w.net, scheme, w.dt, steps, 0, np.arange(threads), threads=threads)
         total += time.perf_counter() - t
     ss = 2 * w.net.n * steps * threads
-    out = {"value": ss / total, "unit": "station-steps/s", "cores": threads, "kind": "oracle",
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"value": ss / total, "unit": "station-steps/s", "cores": threads, "kind": "oracle", "cpu_model": model,
+           "host_cpus": os.cpu_count(),
            "sample": f"both schemes, replications 0..{threads - 1}, first {steps} of {K} steps, "
                      f"{w.net.n} stations ({ss:.3g} station-steps, {total:.1f} s)"}
     # one core: replication 0, backward scheme, about a tenth of the time above
