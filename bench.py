@@ -118,9 +118,16 @@ def parse():
                     help="run only the error-order study of the backward, forward and average schemes")
     ap.add_argument("--fd-check", action="store_true",
                     help="run only the finite-difference check of the gradient at full size (several minutes)")
+    ap.add_argument("--fd-seed", type=int, default=0,
+                    help="Philox seed of the finite-difference check's runs (independent draws per seed)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("DIR", "KERNEL_REGEX"),
                     help="sum rocprofv3 counter CSVs under DIR over the kernels matching KERNEL_REGEX (no GPU)")
     return ap.parse_args()
+
+
+def log(msg: str) -> None:
+    """Progress on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def copy_calibration(mb: int) -> None:
@@ -149,7 +156,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.fd_check:
-        fd_check()
+        fd_check(seed=args.fd_seed)
         return
     if args.error_order:
         error_order()
@@ -183,9 +190,11 @@ def main():
             eb.eq_stats_reduce(net.handle, eb.C.byref(res.desc), res.sums.data_ptr(), res.state.data_ptr(), None,
                                stats[s].data_ptr(), stream.cuda_stream)
 
+    log(f"main workload: {args.warmup} warm-up and {args.steps} timed steps")
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
+    log("warm-up done")
     rc = eb.eq_sim_check(net.handle, stream.cuda_stream)
     if rc != 0:
         raise SystemExit(f"device flags after warmup: {eb.eq_last_error().decode()}")
@@ -195,8 +204,10 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         one_step(ev[k])
+        log(f"timed step {k + 1} queued")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log("timed steps done")
     if eb.eq_sim_check(net.handle, stream.cuda_stream) != 0:
         raise SystemExit(f"device flags: {eb.eq_last_error().decode()}")
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -250,15 +261,21 @@ def main():
         out["note"] = "reduced horizon (testing only)"
     if not args.main_only:
         out["average_scheme"] = bench_pair(w, K, net, sweep_ms)
+        log("average scheme done")
         out["staffing"] = bench_staffing(w, K, sweep_ms)
         out["host_buffers"] = bench_host_buffers(w, K, sweep_ms)
+        log("staffing and host buffers done")
         out["sojourn"] = bench_sojourn()
+        log("sojourn done")
     if not (args.skip_batch or args.main_only):
         out["batching"] = bench_batching(args.per_net_stride)
+        log("batching done")
     if not (args.skip_grad or args.main_only):
         out["gradient"] = bench_gradient()
+        log("gradient done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, K, args.cpu_seconds)
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
@@ -301,14 +318,18 @@ def bench_batching(stride: int) -> dict:
     batched = ss_all / batch_s
     # per network: every `stride`-th network, its own autotuned launch shape, one after another
     sample = list(range(0, len(ws), stride))
+    log(f"batch run done; tuning {len(sample)} networks for the per-network baseline")
     shapes = [eb.tune(nets[k], eb.EQ_BACKWARD, dt, ks[k], reps, 0, trial_steps=32) for k in sample]
+    log("per-network tuning done")
     bufs = [(torch.empty((nets[k].n, reps), dtype=torch.int32, device="cuda"),
              torch.empty((3, nets[k].n, eb.n_tiles(reps)), dtype=torch.int64, device="cuda")) for k in sample]
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for (st, sm), k, shape in zip(bufs, sample, shapes):
+    for i, ((st, sm), k, shape) in enumerate(zip(bufs, sample, shapes)):
         eb.simulate(nets[k], eb.EQ_BACKWARD, dt, ks[k], reps, 0, net_id=ids[k], state=st, sums=sm, check=False,
                     **shape)
+        if i % 64 == 63:
+            log(f"per-network runs queued: {i + 1} of {len(sample)}")
     torch.cuda.synchronize()
     per_s = time.perf_counter() - t
     ss_sample = sum(ws[k].net.n * ks[k] for k in sample) * reps
@@ -391,6 +412,12 @@ def bench_gradient() -> dict:
 
     def med(se_, g_, sel=slice(None)):
         return float(np.median(se_[sel] / np.maximum(np.abs(g_[sel]), 1e-300)))
+
+    def powered(se_, g_, sel=slice(None)):
+        """share of the parameters whose estimate is at least 3.33 standard errors from zero"""
+        return float(np.mean(se_[sel] < 0.3 * np.abs(g_[sel])))
+
+    live = sef[:n] > 0           # parameters with a nonzero score somewhere (a station that served someone)
     return {"workload": "1000-station DAG, 8192 replications, 20000 steps, backward scheme; cost = sum_i hold_i "
                         "mean (N_i - m_i)^+ + sum_i k_i m_i, hold ~ U(1, 5), k ~ U(0.1, 1); 1000 mu + 50 lambda0",
             "forward_ms": round(times["forward"], 1), "grad_ms": round(times["forward_score_reduce"], 1),
@@ -401,9 +428,13 @@ def bench_gradient() -> dict:
             "median_grad_se_over_abs_mu": med(se, g, slice(0, n)),
             "median_grad_se_over_abs_lambda0": med(se, g, slice(n, None)),
             "reach_reduce_ms": round(reach_ms, 3), "full_reduce_ms": round(full_ms, 3),
+            "share_powered_mu": powered(se, g, slice(0, n)), "share_powered_lambda0": powered(se, g, slice(n, None)),
             "full_cost_estimator": {"median_grad_se_over_abs": med(sef, gf),
                                     "median_grad_se_over_abs_mu": med(sef, gf, slice(0, n)),
-                                    "median_se_ratio_reach_over_full_mu": float(np.median(se[:n] / sef[:n]))}}
+                                    "share_powered_mu": powered(sef, gf, slice(0, n)),
+                                    "share_powered_lambda0": powered(sef, gf, slice(n, None))},
+            "se_ratio_reach_over_full_mu_quantiles": [float(q) for q in np.quantile(se[:n][live] / sef[:n][live],
+                                                                                    [0.1, 0.5, 0.9])]}
 
 
 def bench_pair(w, K, net, sweep_ms) -> dict:
@@ -633,14 +664,15 @@ def relative_error_vs_servers(T: float = 1000.0, reps: int = 1024) -> None:
                       "average": [r["average"] for r in rows], "bound": [r["bound"] for r in rows]}), flush=True)
 
 
-def fd_check(rel: float = 1e-3) -> None:
+def fd_check(rel: float = 1e-3, seed: int = 0) -> None:
     """Likelihood-ratio gradient of the 1000-station cost (8192 replications, full horizon,
     backward scheme) against common-random-number central differences: 8 mu coordinates at
     spread DAG depths, 4 lambda0 coordinates and 4 random directions v, each the derivative of
     J along theta * v with the parameters perturbed by +-rel relative.  The estimate is the
     reachability-pruned one (each score against the cost of the stations its parameter can
-    reach); the full-cost estimate is reported beside it.  One JSON line per check, then a
-    summary line."""
+    reach); the full-cost estimate is reported beside it.  `seed` keys every run (the score run
+    and both difference runs), so two seeds give independent repetitions of every check.  One
+    JSON line per check, then a summary line."""
     import math
     import numpy as np
     import torch
@@ -648,10 +680,10 @@ def fd_check(rel: float = 1e-3) -> None:
     from paper_2402_13259_amd import binding as eb, lr
     w = netgen.config5()
     hold, staff = netgen.config5_costs(w.net.n)
-    prob = lr.CostProblem(w.net, hold, staff, w.dt, w.K, w.reps, seed=0)
+    prob = lr.CostProblem(w.net, hold, staff, w.dt, w.K, w.reps, seed=seed)
     n, R, K = w.net.n, w.reps, w.K
     net = eb.Net(w.net)
-    res = eb.simulate_scores(net, eb.EQ_BACKWARD, w.dt, K, R, 0)
+    res = eb.simulate_scores(net, eb.EQ_BACKWARD, w.dt, K, R, seed)
     hold_d = torch.as_tensor(hold, device="cuda")
     f, ms = eb.cost_reduce(hold_d, res.sumq, K)
     g_reach, _ = eb.grad_reduce_reach(net, hold_d, res.sumq, res.score, K)
@@ -696,7 +728,7 @@ def fd_check(rel: float = 1e-3) -> None:
         rows.append(row)
         print(json.dumps(row), flush=True)
     zs = [r["z"] for r in rows]
-    print(json.dumps({"fd_check": "grad1000", "checks": len(zs), "max_abs_z": max(abs(z) for z in zs),
+    print(json.dumps({"fd_check": "grad1000", "seed": seed, "checks": len(zs), "max_abs_z": max(abs(z) for z in zs),
                       "within_3_se": sum(abs(z) < 3 for z in zs), "relative_step": rel,
                       "with_power": sum(r["combined_se_over_abs_fd"] is not None and r["combined_se_over_abs_fd"] < 0.3
                                         for r in rows),
