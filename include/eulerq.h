@@ -156,13 +156,17 @@ typedef struct {
  * one stream, or synchronise between runs made on different streams. */
 size_t eq_sim_workspace_bytes(const eq_net *net, const eq_run_desc *desc);
 
+/* Replications per statistics tile of the d_sums outputs: tiles = ceil(reps / EQ_STAT_TILE_REPS). */
+#define EQ_STAT_TILE_REPS 32
+
 /* Run the scheme on the GPU (asynchronous on `stream`).
  * d_init  device int32 [n][reps] initial state N_0, or NULL for an empty system
  *         (Assumption 1: initially idle).  Must not alias d_state.
  * d_state device int32 [n][reps] (replication index fastest): receives N_K.
- * d_sums  device int64 [3][n][tiles], tiles = ceil(reps / 64), or NULL: for every station and
- *         tile of 64 consecutive replications of this run (the last tile may be short), the
- *         sums over those replications and over tau = 1..K of N_tau, (N_tau - m_i)^+ and D_tau.
+ * d_sums  device int64 [3][n][tiles], tiles = ceil(reps / EQ_STAT_TILE_REPS), or NULL: for
+ *         every station and tile of 32 consecutive replications of this run (the last tile may
+ *         be short), the sums over those replications and over tau = 1..K of N_tau,
+ *         (N_tau - m_i)^+ and D_tau.
  * The first call on a network for a given (dt, K) uploads its tables (synchronously).
  * Errors: EQ_EINVAL, EQ_ENOTDAG (forward scheme on a non index-ordered DAG), EQ_ENOMEM,
  * EQ_EDEVICE. */
@@ -198,7 +202,7 @@ int eq_sim_run_host(eq_net *net, const eq_run_desc *desc, const int32_t *init, i
  * d_out device double [6][n]: mean N, standard error of mean N, mean queue length (N-m)^+,
  * its standard error, throughput (departures per unit time) and mean waiting time in queue
  * by Little's law, sum (N-m)^+ dt / (number of arrivals), arrivals = N_K - N_0 + sum D.
- * Standard errors treat the 64-replication tiles' time averages as independent samples
+ * Standard errors treat the 32-replication tiles' time averages as independent samples
  * (weighted by tile size; 0 when the run has a single tile).  With n_steps = 0 the means,
  * standard errors and throughput are 0; the waiting time is 0 where no customer arrived.
  * d_init may be NULL (empty start). */

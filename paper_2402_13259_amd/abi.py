@@ -10,7 +10,8 @@ EQ_BACKWARD, EQ_FORWARD = 0, 1
 EQ_DEP_EXACT, EQ_DEP_NAIVE = 0, 1
 EQ_SHAPE_CONST, EQ_SHAPE_SINUSOID = 0, 1
 EQ_KERNEL_AUTO, EQ_KERNEL_TILE, EQ_KERNEL_SWEEP = 0, 1, 2
-TILE_REPS = 64
+STAT_TILE_REPS = 32       # EQ_STAT_TILE_REPS: replications per statistics tile of the sums
+EQ_NOALLOC_SCRATCH_BYTES = 64 << 20   # static scratch of eq_sim_run_noalloc
 
 EXPORTS = ["eq_net_create", "eq_net_destroy", "eq_net_set_staffing", "eq_net_set_params", "eq_sim_run_host", "eq_net_tables", "eq_net_levels", "eq_sim_workspace_bytes",
            "eq_sim_run", "eq_sim_run_noalloc", "eq_sim_tune", "eq_sim_run_pair", "eq_stats_reduce", "eq_stats_reduce_pair",

@@ -159,13 +159,13 @@ class Net:
 class RunResult:
     """A run: final states [n, reps] int32, tile sums [3, n, tiles] int64 (or None) and its descriptor."""
     state: "object"      # torch int32 [n, reps]
-    sums: "object"       # torch int64 [3, n, tiles] (64-replication tiles) or None
+    sums: "object"       # torch int64 [3, n, tiles] (32-replication statistics tiles) or None
     desc: eq_run_desc
 
 
 def n_tiles(reps: int) -> int:
-    """Number of 64-replication tiles of the statistics sums."""
-    return (int(reps) + TILE_REPS - 1) // TILE_REPS
+    """Number of statistics tiles (EQ_STAT_TILE_REPS replications each) of the sums."""
+    return (int(reps) + STAT_TILE_REPS - 1) // STAT_TILE_REPS
 
 
 def make_desc(scheme: int, dt: float, K: int, reps: int, seed: int = 0, dep_mode: int = EQ_DEP_EXACT,

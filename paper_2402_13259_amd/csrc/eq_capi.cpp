@@ -551,6 +551,7 @@ eq::NetView make_view(const eq_net &net, const eq_run_desc &d, int32_t *state, i
   v.reps = d.reps;
   v.rep0 = d.rep0;
   v.tiles = (d.reps + eq::kTileReps - 1) / eq::kTileReps;
+  v.stiles = eq::stat_tiles(d.reps);
   v.extra = d.scheme == EQ_FORWARD ? (int)net.level_ptr.size() - 2 : 0;
   v.k0 = (uint32_t)d.seed;
   v.k1 = (uint32_t)(d.seed >> 32) ^ d.net_id;
@@ -764,7 +765,7 @@ int run_sim(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t
   Shape sh{};
   if (kernel == EQ_KERNEL_TILE && (rc = choose_shape(*net, *desc, &sh))) return rc;
   if ((rc = ensure_net_device(*net, desc->dt, desc->n_steps))) return rc;
-  const int tiles = (desc->reps + eq::kTileReps - 1) / eq::kTileReps;
+  const int tiles = eq::stat_tiles(desc->reps);
   const long long nsums = 3LL * net->n * tiles;
   const uint32_t k0 = (uint32_t)desc->seed, k1 = (uint32_t)(desc->seed >> 32) ^ desc->net_id;
   hipError_t e;
@@ -857,6 +858,7 @@ int eq_sim_run(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int3
 }
 
 static_assert(EQ_NOALLOC_SCRATCH_BYTES == eq::kNoAllocScratchBytes, "scratch size of the header and the kernels");
+static_assert(EQ_STAT_TILE_REPS == eq::kStatReps, "statistics tile of the header and the kernels");
 
 int eq_sim_run_noalloc(eq_net *net, const eq_run_desc *desc, const int32_t *d_init, int32_t *d_state,
                        int64_t *d_sums, void *stream) {
@@ -886,7 +888,7 @@ int eq_sim_run_host(eq_net *net, const eq_run_desc *desc, const int32_t *init, i
   int rc = check_desc(net, desc);
   if (rc) return rc;
   const size_t cells = (size_t)net->n * (size_t)desc->reps;
-  const size_t tiles = ((size_t)desc->reps + 63) / 64;
+  const size_t tiles = (size_t)eq::stat_tiles(desc->reps);
   int32_t *d_init = nullptr, *d_state = nullptr;
   int64_t *d_sums = nullptr;
   double *d_stats = nullptr;
@@ -1135,7 +1137,7 @@ int eq_sim_run_pair(eq_net *net, const eq_run_desc *desc, const int32_t *d_init,
   a.dep_mode = desc->dep_mode;
   a.dt = desc->dt;
   const long long nstate = (long long)net->n * desc->reps;
-  const long long nsums = d_sums_b ? 3LL * net->n * a.vb.tiles : 0;
+  const long long nsums = d_sums_b ? 3LL * net->n * a.vb.stiles : 0;
   if ((e = eq::launch_sweep_init(d_state_b, d_init, nstate, ring_b, slots_b * desc->reps, a.vb.tsums, nsums, st)) !=
           hipSuccess ||
       (e = eq::launch_sweep_init(d_state_f, d_init, nstate, ring_f, slots_f * desc->reps, a.vf.tsums, nsums, st)) !=
@@ -1364,7 +1366,7 @@ void eq_batch_destroy(eq_batch *b) { delete b; }
 
 int eq_batch_layout(const eq_batch *b, int32_t reps, int64_t *state_off, int64_t *sums_off) {
   if (!b || reps < 1) return fail(EQ_EINVAL, "null batch or reps < 1");
-  const int64_t tiles = (reps + eq::kTileReps - 1) / eq::kTileReps;
+  const int64_t tiles = eq::stat_tiles(reps);
   int64_t so = 0, mo = 0;
   for (size_t k = 0; k < b->nets.size(); ++k) {
     if (state_off) state_off[k] = so;

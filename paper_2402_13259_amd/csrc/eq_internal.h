@@ -59,7 +59,7 @@ struct SimArgs {
   const int *seg_m;        // [n_seg][n] servers per segment
   const float *seg_rate;   // [n_seg][n] fp32(m mu) per segment
   int *state;              // [n][reps]
-  long long *sums;         // [3][n][tiles] tile sums (64 replications per tile) or nullptr
+  long long *sums;         // [3][n][tiles] statistics tile sums (kStatReps replications per tile) or nullptr
   unsigned *flags;         // sticky: bit0 state limit / block budget, bit1 retry cap
   int n, K, reps, rep0, R, log2R, items, n_levels, dep_mode, tiles;
   float dt;
@@ -79,7 +79,7 @@ struct NetView {
   const float *seg_rate;   // [n_seg][n]
   int *N;                  // [n][reps] state
   int *ring;               // inflow slots [sum depth][reps]
-  long long *tsums;        // [3][n][tiles] or nullptr
+  long long *tsums;        // [3][n][stiles] statistics tile sums or nullptr
   // score runs only (nullptr otherwise)
   const ScoreParam *scp;   // [n]
   float *smu;              // [n][reps] summed departure scores in mu_i
@@ -89,7 +89,9 @@ struct NetView {
   int *rec_N, *rec_D;      // [rec_len][n][reps] N_tau, D_tau
   int *rec_R;              // [rec_len][nnz][reps] routed count per edge
   int rec_t0, rec_len, nnz;
-  int n, K, reps, rep0, tiles, extra;   // extra: launches beyond K (forward: levels - 1)
+  int n, K, reps, rep0, tiles, extra;   // tiles: 64-replication tasks per station; extra:
+                                        // launches beyond K (forward: levels - 1)
+  int stiles;              // statistics tiles, ceil(reps / kStatReps)
   uint32_t k0, k1;         // Philox key
 };
 
@@ -123,7 +125,11 @@ struct BatchArgs {
   unsigned *flags;
 };
 
-constexpr int kTileReps = 64;   // replications per statistics tile (one wavefront)
+constexpr int kTileReps = 64;   // replications per sweep task (one wavefront)
+// Replications per statistics tile: half a wavefront, so that a run of 1024 replications
+// has 32 tile means for its standard errors.
+constexpr int kStatReps = 32;
+__host__ __device__ constexpr int stat_tiles(int reps) { return (reps + kStatReps - 1) / kStatReps; }
 
 hipError_t launch_sweep_init(int *N, const int *init, long long nstate, int *ring, long long nring,
                              long long *tsums, long long nsums, hipStream_t st);

@@ -5,9 +5,10 @@
 // horizon -- the state N (int32, replication fastest), the step's departures, and int32
 // partial sums of N, (N - m)^+ and D -- so the hot loop touches HBM only for the read-only
 // network tables (cache resident) and for statistics flushes every 16 steps into the
-// int64 per-(station, 64-replication tile) sums [3][n][tiles] (atomic integer adds).
-// This path suits networks small enough for a tile of >= 16 replications to fit in LDS.  Items are (station, rep) pairs, consecutive lanes taking consecutive
-// replications of one station; a thread walks items tid, tid + B, ...
+// int64 per-(station, 32-replication statistics tile) sums [3][n][tiles] (atomic integer
+// adds).  This path suits networks small enough for a tile of >= 16 replications to fit in
+// LDS.  Items are (station, rep) pairs, consecutive lanes taking consecutive replications of
+// one station; a thread walks items tid, tid + B, ...
 //
 // Backward scheme (Algorithm 1), two phases per step separated by barriers:
 //   1. each item reads x = N_{tau-1} (its own entry only), draws D = GenerateDeparture(x)
@@ -100,7 +101,7 @@ __device__ __forceinline__ void init_tile(const SimArgs &a, int *N, int *PN, int
 
 // index of the (station, tile) statistics sum of an item
 __device__ __forceinline__ long long tile_index(const SimArgs &a, int s, int rep) {
-  return (long long)s * a.tiles + (rep >> 6);
+  return (long long)s * a.tiles + rep / kStatReps;
 }
 
 __global__ __launch_bounds__(1024) void k_backward(SimArgs a) {
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(1024) void k_forward(SimArgs a) {
   if (flags) atomicOr(a.flags, flags);
 }
 
-// Per-station reduction over the 64-replication tiles; one workgroup per station, fixed
+// Per-station reduction over the 32-replication statistics tiles; one workgroup per station, fixed
 // tree order.  Means are exact integer totals divided once; the standard error treats the
 // tile means as independent samples, weighted by tile size (equal weights for full tiles).
 constexpr int kStatThreads = 256;
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(kStatThreads) void k_stats(const long long *tsums, 
   __shared__ long long red_i[4][kStatThreads];
   __shared__ double red_d[2][kStatThreads];
   const int s = blockIdx.x, tid = threadIdx.x;
-  const int tiles = (reps + 63) / 64;
+  const int tiles = stat_tiles(reps);
   const long long plane = (long long)n * tiles;
   const long long *sN = tsums + (long long)s * tiles, *sQ = sN + plane, *sD = sN + 2 * plane;
   const long long *sN2 = tsums2 ? tsums2 + (long long)s * tiles : nullptr;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(kStatThreads) void k_stats(const long long *tsums, 
   double vn = 0.0, vq = 0.0;
   if (K > 0) {
     for (int t = tid; t < tiles; t += kStatThreads) {
-      const double c = (double)min(64, reps - 64 * t);
+      const double c = (double)min(kStatReps, reps - kStatReps * t);
       const double w = c / R;
       const double dn = (double)tile_n(t) / (c * Ke) - mN;
       const double dq = (double)tile_q(t) / (c * Ke) - mQ;

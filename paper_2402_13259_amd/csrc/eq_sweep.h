@@ -22,22 +22,22 @@
 // step, so all stations advance in every launch and the DAG depth costs L - 1 extra
 // launches instead of a barrier per level and step.
 //
-// Statistics: each task reduces N, (N - m)^+ and D over its 64 lanes (64-bit shuffles) and
-// one lane adds them to int64 sums [3][n][tiles].
+// Statistics: each task reduces N, (N - m)^+ and D over each half of its 64 lanes (64-bit
+// shuffles) and lanes 0 and 32 add them to the int64 sums [3][n][stiles] of their 32-replication
+// statistics tiles.
 #pragma once
 #include "eq_device.h"
 #include "eq_internal.h"
 
 namespace eq {
 
-// Sum over the 64 lanes.  Values are below 2^27, so groups of 16 lanes sum exactly in
-// int32; the last two levels run in int64.
-__device__ __forceinline__ long long wave_sum(int v) {
+// Sum over each half (lanes 0..31, 32..63) of the wavefront.  Values are below 2^27, so
+// groups of 16 lanes sum exactly in int32; the last level runs in int64.
+__device__ __forceinline__ long long half_sum(int v) {
 #pragma unroll
   for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
   long long w = v;
   w += __shfl_xor(w, 16, 64);
-  w += __shfl_xor(w, 32, 64);
   return w;
 }
 
@@ -68,12 +68,15 @@ __device__ __forceinline__ bool task_of(const NetView &v, TaskPos &tp) {
   return true;
 }
 
+// Task (s, t) covers statistics tiles 2t and 2t + 1 (the second is absent when the last task
+// holds 32 replications or fewer); each belongs to this task alone within a launch.
 __device__ __forceinline__ void add_tile_stats(const NetView &v, int s, int t, int xn, int xq, int xd,
                                                int lane) {
-  const long long vn = wave_sum(xn), vq = wave_sum(xq), vd = wave_sum(xd);
-  if (lane == 0) {
-    const long long plane = (long long)v.n * v.tiles;
-    long long *p = v.tsums + (long long)s * v.tiles + t;
+  const long long vn = half_sum(xn), vq = half_sum(xq), vd = half_sum(xd);
+  const int st = 2 * t + (lane >> 5);
+  if ((lane & 31) == 0 && st < v.stiles) {
+    const long long plane = (long long)v.n * v.stiles;
+    long long *p = v.tsums + (long long)s * v.stiles + st;
     p[0] += vn;
     p[plane] += vq;
     p[2 * plane] += vd;

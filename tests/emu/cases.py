@@ -66,8 +66,11 @@ def desc(scheme, dt, K, reps, seed, kernel=abi.EQ_KERNEL_AUTO, **kw):
                            d["block"])
 
 
+STAT = 32   # replications per statistics tile (EQ_STAT_TILE_REPS)
+
+
 def tiles(reps):
-    return (reps + 63) // 64
+    return (reps + STAT - 1) // STAT
 
 
 def run(net, d):
@@ -83,7 +86,7 @@ def assert_run_equals_oracle(w, scheme, dt, K, reps, seed, st, sums):
     assert np.array_equal(st.T, ref["final"]), "final states differ from the oracle"
     for k, name in enumerate(("sumN", "sumQ", "sumD")):
         for t in range(tiles(reps)):
-            assert np.array_equal(sums[k, :, t], ref[name][64 * t:64 * (t + 1)].sum(0)), (name, t)
+            assert np.array_equal(sums[k, :, t], ref[name][STAT * t:STAT * (t + 1)].sum(0)), (name, t)
 
 
 def staffed(w):

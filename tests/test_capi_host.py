@@ -43,6 +43,15 @@ def test_exports_every_declared_symbol(eb):
     assert sorted(eb.EXPORTS) == names
 
 
+def test_header_constants_match_the_binding(eb):
+    """The binding's copies of the header's size constants (statistics tile, scratch size)."""
+    txt = open(os.path.join(ROOT, "include", "eulerq.h")).read()
+    defs = dict(re.findall(r"#define (EQ_[A-Z_]+) \(?([0-9a-z<> ]+)\)?\n", txt))
+    assert int(defs["EQ_STAT_TILE_REPS"]) == eb.STAT_TILE_REPS == 32
+    assert eval(defs["EQ_NOALLOC_SCRATCH_BYTES"].replace("ll", "")) == eb.EQ_NOALLOC_SCRATCH_BYTES
+    assert eb.n_tiles(1000) == 32 and eb.n_tiles(1024) == 32 and eb.n_tiles(1025) == 33 and eb.n_tiles(1) == 1
+
+
 def make(eb, n, row_ptr, col, prob, servers, mu, src=(0,), lam=(1.0,), shape=0, amp=0.0, period=1.0, knots=None):
     arrs = [np.asarray(row_ptr, np.int32), np.asarray(col, np.int32), np.asarray(prob, np.float32),
             np.asarray(servers, np.int32), np.asarray(mu, np.float32), np.asarray(src, np.int32),

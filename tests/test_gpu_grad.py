@@ -102,15 +102,16 @@ def test_score_run_full_size_sampled_reps(eb):
     w = netgen.config5()
     hold, staff = netgen.config5_costs(w.net.n)
     net, res = score_run(eb, w.net, 0, w.dt, w.K, w.reps, seed=0)
-    tile = 93   # one whole 64-replication tile, its sums over the full horizon
-    rows = np.r_[0, 1, 4095, 4096, 8191, tile * 64:(tile + 1) * 64]
+    wave = 93   # one wavefront's 64 replications: two whole 32-replication statistics tiles
+    rows = np.r_[0, 1, 4095, 4096, 8191, wave * 64:(wave + 1) * 64]
     ref = oracle.run(w.net, 0, w.dt, w.K, 0, rows, scores=True)
     assert_scores_equal(res, ref, w.net.n, rows)
-    sums = res.sums.cpu().numpy()[:, :, tile]
-    sel = rows // 64 == tile
-    for k, name in enumerate(("sumN", "sumQ", "sumD")):
-        assert np.array_equal(sums[k], ref[name][sel].sum(0)), name
-    assert (ref["sumQ"][sel].sum(0) > 0).mean() > 0.5
+    for tile in (2 * wave, 2 * wave + 1):
+        sums = res.sums.cpu().numpy()[:, :, tile]
+        sel = rows // 32 == tile
+        for k, name in enumerate(("sumN", "sumQ", "sumD")):
+            assert np.array_equal(sums[k], ref[name][sel].sum(0)), (name, tile)
+    assert (ref["sumQ"][rows // 64 == wave].sum(0) > 0).mean() > 0.5
     f, ms = eb.cost_reduce(torch.as_tensor(hold, device="cuda"), res.sumq, w.K)
     g, se = eb.grad_reduce(f, ms, res.score)
     f_np = res.sumq.cpu().numpy().T.astype(np.float64) @ hold / w.K

@@ -23,6 +23,7 @@ def eb():
 
 
 KERNELS = [1, 2]   # EQ_KERNEL_TILE, EQ_KERNEL_SWEEP
+STAT = 32          # replications per statistics tile of the sums (EQ_STAT_TILE_REPS)
 
 
 def gpu_run(eb, net_obj, w, scheme, K, reps, seed=0, **kw):
@@ -38,8 +39,8 @@ def gpu_run(eb, net_obj, w, scheme, K, reps, seed=0, **kw):
 def tile_sums(per_rep: np.ndarray, rep_ids: np.ndarray) -> dict:
     """Oracle per-replication sums [len(rep_ids), n] -> {tile: sum over its replications}."""
     out = {}
-    for t in np.unique(rep_ids // 64):
-        out[int(t)] = per_rep[rep_ids // 64 == t].sum(0)
+    for t in np.unique(rep_ids // STAT):
+        out[int(t)] = per_rep[rep_ids // STAT == t].sum(0)
     return out
 
 
@@ -133,11 +134,12 @@ def test_tandem_all_reps(eb, scheme, kernel):
     st = eb.station_stats(net, res).cpu().numpy()
     K, R, dt = w.K, w.reps, float(np.float32(w.dt))
     reps = np.arange(R)
-    cnt = np.bincount(reps // 64).astype(float)
+    cnt = np.bincount(reps // STAT).astype(float)
     T = len(cnt)
+    assert T == 32          # 1000 replications: 32 tile means behind each standard error
 
     def se(per_rep):
-        tsum = np.stack([per_rep[reps // 64 == t].sum(0) for t in range(T)])
+        tsum = np.stack([per_rep[reps // STAT == t].sum(0) for t in range(T)])
         m_t = tsum / (cnt[:, None] * K)
         m = per_rep.sum(0) / (R * K)
         return np.sqrt((((cnt / R)[:, None] * (m_t - m)) ** 2).sum(0) * T / (T - 1))
@@ -157,22 +159,22 @@ def test_layered_full_size_sampled_reps(eb, scheme, kernel):
     net, res, state, sums = gpu_run(eb, w.net, w, scheme, w.K, w.reps, seed=0, kernel=kernel)
     rows = np.r_[0:4, 4992:4996, 9984:10000]
     ref = oracle.run(w.net, scheme, w.dt, w.K, 0, rows)
-    assert_same(state, sums, ref, rows, full_tiles=[156])
+    assert_same(state, sums, ref, rows, full_tiles=[9984 // STAT])
 
 
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_dag1000_full_size_sampled_reps(eb, scheme):
     """Full size (1000 stations, 20000 steps, 4096 replications) in the launch configuration
     the benchmark times: final states of sampled replications bit-exact, and the int64 sums of
-    N, (N - m)^+ and D over the whole horizon of one full 64-replication tile (replications
-    2624..2687) bit-exact: the statistics the benchmark reports, after the queues have built
-    up through several arrival peaks."""
+    N, (N - m)^+ and D over the whole horizon of one wavefront's 64 replications (2624..2687,
+    two statistics tiles) bit-exact: the statistics the benchmark reports, after the queues
+    have built up through several arrival peaks."""
     w = netgen.config3()
     net, res, state, sums = gpu_run(eb, w.net, w, scheme, w.K, w.reps, seed=0)
-    tile = 41
-    rows = np.r_[0:3, 2047:2049, 4095:4096, tile * 64:(tile + 1) * 64]
+    wave = 41
+    rows = np.r_[0:3, 2047:2049, 4095:4096, wave * 64:(wave + 1) * 64]
     ref = oracle.run(w.net, scheme, w.dt, w.K, 0, rows)
-    assert_same(state, sums, ref, rows, full_tiles=[tile])
+    assert_same(state, sums, ref, rows, full_tiles=[2 * wave, 2 * wave + 1])
     # the long horizon reaches the queueing branch of Algorithm 3 on most stations
     assert (ref["sumQ"].sum(0) > 0).mean() > 0.5
 
@@ -394,16 +396,16 @@ def test_sim_tune(eb, scheme):
 # ---------------------------------------------------------------------------------------
 def pooled_stats(ref_b, ref_f, reps, K, dt, init=None):
     """Average-scheme statistics from the oracle's per-replication sums of both schemes."""
-    R, T = reps, (reps + 63) // 64
+    R, T = reps, (reps + STAT - 1) // STAT
     rid = np.arange(R)
-    cnt = np.bincount(rid // 64).astype(float)
+    cnt = np.bincount(rid // STAT).astype(float)
     Ke = 2 * K
 
     def pooled(name):
         return ref_b[name] + ref_f[name]
 
     def se(per_rep):
-        tsum = np.stack([per_rep[rid // 64 == t].sum(0) for t in range(T)])
+        tsum = np.stack([per_rep[rid // STAT == t].sum(0) for t in range(T)])
         m_t = tsum / (cnt[:, None] * Ke)
         m = per_rep.sum(0) / (R * Ke)
         return np.sqrt((((cnt / R)[:, None] * (m_t - m)) ** 2).sum(0) * T / (T - 1))
@@ -502,7 +504,7 @@ def test_staffing_layered_daily_schedule(eb, scheme):
     net, res, state, sums = gpu_run(eb, w, h, scheme, K, reps, seed=4)
     rows = np.r_[0:64, 500:503, 999]
     ref = oracle.run(w, scheme, h, K, 4, rows)
-    assert_same(state, sums, ref, rows, full_tiles=[0])
+    assert_same(state, sums, ref, rows, full_tiles=[0, 1])
 
 
 def test_staffing_scores_and_batch(eb):
@@ -794,7 +796,7 @@ def test_bad_tensors_are_refused(eb):
              (ValueError, dict(init=torch.zeros((n, reps + 1), dtype=torch.int32, device="cuda"))),
              (ValueError, dict(init=torch.zeros((reps, n), dtype=torch.int32, device="cuda").t())),
              (ValueError, dict(state=torch.zeros((n, reps), dtype=torch.float32, device="cuda"))),
-             (ValueError, dict(sums=torch.zeros((3, n, 2), dtype=torch.int64, device="cuda")))]
+             (ValueError, dict(sums=torch.zeros((3, n, 1), dtype=torch.int64, device="cuda")))]   # 2 tiles
     for exc, kw in cases:
         with pytest.raises(exc):
             eb.simulate(net, 0, w.dt, 5, reps, 1, **kw)
@@ -1060,9 +1062,9 @@ def stats_definition(ref, reps, K, dt, init):
     """Per-station statistics by their definitions on the oracle's per-replication sums:
     means over K station-steps per replication; standard errors from the tile means weighted
     by tile size (0 for one tile); throughput; Little's-law waiting time (0 without arrivals)."""
-    R, T = reps, (reps + 63) // 64
+    R, T = reps, (reps + STAT - 1) // STAT
     rid = np.arange(R)
-    cnt = np.bincount(rid // 64).astype(float)
+    cnt = np.bincount(rid // STAT).astype(float)
     n = ref["final"].shape[1]
     if K == 0:
         out = np.zeros((6, n))
@@ -1070,7 +1072,7 @@ def stats_definition(ref, reps, K, dt, init):
         def se(per_rep):
             if T < 2:
                 return np.zeros(n)
-            tsum = np.stack([per_rep[rid // 64 == t].sum(0) for t in range(T)])
+            tsum = np.stack([per_rep[rid // STAT == t].sum(0) for t in range(T)])
             m_t = tsum / (cnt[:, None] * K)
             m = per_rep.sum(0) / (R * K)
             return np.sqrt((((cnt / R)[:, None] * (m_t - m)) ** 2).sum(0) * T / (T - 1))
