@@ -236,7 +236,7 @@ def tables(net, dt: float, K: int) -> dict:
 
 
 def sampler_tables() -> tuple[np.ndarray, np.ndarray]:
-    inv = np.zeros(128, np.float32)
+    inv = np.zeros(256, np.float32)
     fc = np.zeros(10, np.float32)
     lib().orc_get_tables(_ptr(inv), _ptr(fc))
     return inv, fc

@@ -88,7 +88,7 @@ enum {
     EV_PTRS,           /* Poisson draws by PTRS */
     EV_PTRS_TRY,       /*   attempts */
     EV_PTRS_SLOW,      /*   attempts that reach the logarithmic test */
-    EV_BIN_INV,        /* binomial draws by inversion (n p < 40) */
+    EV_BIN_INV,        /* binomial draws by inversion (n p < 56) */
     EV_BIN_INV_STEP,   /*   their search steps */
     EV_BTRS,           /* binomial draws by BTRS */
     EV_BTRS_TRY,       /*   attempts */
@@ -303,10 +303,10 @@ float orc_expm1f(float x)
 /* Tables shared by the samplers: fp32(1/k) and the Stirling-series remainder  */
 /* fc(j) = ln j! - [(j+1/2) ln(j+1) - (j+1) + ln(2 pi)/2].                      */
 /* ------------------------------------------------------------------------- */
-#define INV_TAB 128
+#define INV_TAB 256
 #define POIS_INV_MAX 63          /* Poisson inversion (lam < 10) stops at k = 63 */
-#define BINOM_INV_MAX 127        /* binomial inversion (n p < 40) stops at k = 127 */
-#define BINOM_INV_NP 40.0f       /* n p below this: inversion, else BTRS */
+#define BINOM_INV_MAX 255        /* binomial inversion (n p < 56) stops at k = 255 */
+#define BINOM_INV_NP 56.0f       /* n p below this: inversion, else BTRS */
 static float INV[INV_TAB];
 static float FC_TAB[10];
 static pthread_once_t tab_once = PTHREAD_ONCE_INIT;
@@ -323,10 +323,10 @@ static void init_tables(void)
     }
 }
 
-void orc_get_tables(float *inv128, float *fc10)
+void orc_get_tables(float *inv256, float *fc10)
 {
     pthread_once(&tab_once, init_tables);
-    if (inv128) memcpy(inv128, INV, sizeof INV);
+    if (inv256) memcpy(inv256, INV, sizeof INV);
     if (fc10) memcpy(fc10, FC_TAB, sizeof FC_TAB);
 }
 
@@ -400,9 +400,9 @@ int32_t orc_poisson(float lam, ustream *S)
     return (int32_t)floorf(lam);
 }
 
-/* Binomial(n, p) for n*p < 40, 0 < p <= 1/2: inversion from k = 0 (one uniform),  */
-/* at most BINOM_INV_MAX steps (P(X > 127) < 1e-25 there).  q^n >= e^-56 stays a     */
-/* normal fp32 number.                                                               */
+/* Binomial(n, p) for n*p < 56, 0 < p <= 1/2: inversion from k = 0 (one uniform),  */
+/* at most BINOM_INV_MAX steps (P(X > 255) < 1e-60 there).  q^n >= e^-78 stays a     */
+/* normal fp32 number (n ln(1/q) <= 2 ln 2 n p for p <= 1/2).                        */
 static int32_t binom_inversion(int32_t n, float p, ustream *S)
 {
     float q = 1.0f - p;
@@ -424,7 +424,7 @@ static int32_t binom_inversion(int32_t n, float p, ustream *S)
     return k;
 }
 
-/* Binomial(n, p) for n*p >= 40, p <= 1/2: transformed rejection with squeeze */
+/* Binomial(n, p) for n*p >= 56, p <= 1/2: transformed rejection with squeeze */
 /* (BTRS of Hormann 1993).  Acceptance compares against ln f(k)/f(m), m the mode. */
 static int32_t binom_btrs(int32_t n, float p, ustream *S)
 {

@@ -198,17 +198,21 @@ __device__ __forceinline__ float rate_in(const int *segidx, const float *seg_rat
 
 // ------------------------------------------------------------------------------------
 // Sampler tables (uploaded by the host at initialisation):
-//   c_rcp[i] = fp32(1/(i+1)), i = 0..127 (16-byte aligned, read four at a time);
+//   c_rcp[i] = fp32(1/(i+1)), i = 0..255 (16-byte aligned, read four at a time);
 //   c_fc[j]  = ln j! - ((j + 1/2) ln(j+1) - (j+1) + ln(2 pi)/2), j = 0..9 (fp64 -> fp32).
 // ------------------------------------------------------------------------------------
-constexpr int kRcpTab = 128;
+constexpr int kRcpTab = 256;
 constexpr int kPoisInvMax = 63;      // Poisson inversion (lam < 10) stops at k = 63
-constexpr int kBinomInvMax = 127;    // binomial inversion (n p < 40) stops at k = 127
-constexpr float kBinomInvNp = 40.0f; // n p below this: inversion, else BTRS
+constexpr int kBinomInvMax = 255;    // binomial inversion (n p < 56) stops at k = 255
+// n p below this: inversion, else BTRS.  Both are exact samplers; the switch sits where a
+// wavefront's cost of the two meets: inversion runs to its slowest lane's k, about n p +
+// 2.4 sqrt(n p) steps over 64 lanes, and BTRS to its slowest lane's attempt, with the
+// logarithmic test taken in nearly every attempt by some lane.
+constexpr float kBinomInvNp = 56.0f;
 extern __constant__ float4 c_rcp4[kRcpTab / 4];
 extern __constant__ float c_fc[10];
 
-__device__ __forceinline__ float rcp_tab(int k) {   // fp32(1/k), 1 <= k <= 128
+__device__ __forceinline__ float rcp_tab(int k) {   // fp32(1/k), 1 <= k <= 256
   return reinterpret_cast<const float *>(c_rcp4)[k - 1];
 }
 
@@ -269,8 +273,9 @@ __device__ __forceinline__ int poisson(float lam, Stream &S, uint32_t &flags) {
   return (int)__builtin_floorf(lam);
 }
 
-// Binomial(n, p), n p < 40, 0 < p <= 1/2: inversion from 0 with the pmf recurrence
-// f_k = f_{k-1} ((n+1) r / k - r), r = p/q, f_0 = e^{n lq}, lq = ln(1 - p), at most 127 steps.  Every lane still searching
+// Binomial(n, p), n p < 56, 0 < p <= 1/2: inversion from 0 with the pmf recurrence
+// f_k = f_{k-1} ((n+1) r / k - r), r = p/q, f_0 = e^{n lq} >= e^-78 (a normal fp32 number),
+// lq = ln(1 - p), at most 255 steps (P(X > 255) < 1e-60).  Every lane still searching
 // is at the same k, so a pass takes four steps with one scalar load of their four
 // reciprocals; a lane stops at exactly the step the one-step search stops at.
 __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, uint32_t &flags) {
@@ -314,7 +319,7 @@ __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, ui
   return k;
 }
 
-// Binomial(n, p), n p >= 40, p <= 1/2: BTRS (Hormann 1993), acceptance against
+// Binomial(n, p), n p >= 56, p <= 1/2: BTRS (Hormann 1993), acceptance against
 // ln f(k)/f(mode) from Stirling's series.
 __device__ __forceinline__ int binom_btrs(int n, float p, float r, Stream &S, uint32_t &flags) {
   const float nf = (float)n;

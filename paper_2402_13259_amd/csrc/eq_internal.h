@@ -5,7 +5,7 @@
 
 namespace eq {
 
-constexpr int kRcpTabHost = 128;   // entries fp32(1/(i+1)), i = 0..127, of the sampler table
+constexpr int kRcpTabHost = 256;   // entries fp32(1/(i+1)), i = 0..255, of the sampler table
 constexpr int kStateLimit = 1 << 27;   // states at or above this raise the sticky flag
 
 // Per-station constants of one run (32 bytes, one record load per item).

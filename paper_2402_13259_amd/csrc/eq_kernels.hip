@@ -356,6 +356,8 @@ __global__ void k_selftest_philox(long long count, const uint32_t *ctr, const ui
 }
 
 // ---- launch helpers (host) ---------------------------------------------------------------
+static_assert(kRcpTab == kRcpTabHost, "reciprocal table of the host and the samplers");
+
 hipError_t upload_sampler_tables(const float *inv, const float *fc) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_rcp4), inv, sizeof(float) * kRcpTab);
   if (e != hipSuccess) return e;

@@ -91,6 +91,7 @@ SAMPLER_CASES = [
     (0, dict(f0=0.3)), (0, dict(f0=9.99)), (0, dict(f0=10.0)), (0, dict(f0=57.3)), (0, dict(f0=4321.0)),
     (1, dict(i0=7, f0=0.2)), (1, dict(i0=40, f0=0.3)), (1, dict(i0=1000, f0=0.01)), (1, dict(i0=9000, f0=0.0049)),
     (1, dict(i0=60, f0=0.8)), (1, dict(i0=100000, f0=0.37)), (1, dict(i0=5, f0=1.0)),
+    (1, dict(i0=560, f0=0.0999)), (1, dict(i0=560, f0=0.1)), (1, dict(i0=114, f0=0.49)),
     (2, dict(i0=1)), (2, dict(i0=3)), (2, dict(i0=50)), (2, dict(i0=20000)),
     (3, dict(i0=5, i1=10, f0=1.0, f1=0.5)), (3, dict(i0=30, i1=10, f0=1.0, f1=0.05)),
     (3, dict(i0=40, i1=20, f0=3.0, f1=0.5)), (3, dict(i0=9000, i1=8000, f0=1.1, f1=0.005)),
@@ -111,9 +112,9 @@ def test_samplers_bit_identical(eb, kind, kw):
     assert np.array_equal(g.view(np.uint32), r.view(np.uint32))
 
 
-@pytest.mark.parametrize("n,p", [(4, 0.45), (2, 0.5), (9, 0.3), (127, 0.25), (200, 0.1)])
+@pytest.mark.parametrize("n,p", [(4, 0.45), (2, 0.5), (9, 0.3), (127, 0.25), (200, 0.1), (255, 0.2), (111, 0.5)])
 def test_binomial_inversion_cap(eb, n, p):
-    """Inversion draws whose step cap (min(n, 127)) can bind: the rare draws whose fp32 cdf at
+    """Inversion draws whose step cap (min(n, 255)) can bind: the rare draws whose fp32 cdf at
     the cap stays below the uniform must stop at the cap on both sides (4M draws each)."""
     count = 1 << 22
     g = eb.selftest_sample(1, count, seed=123, rep0=0, station=7, step0=1, sub=2, i0=n, f0=p).cpu().numpy()

@@ -122,8 +122,8 @@ def test_expm1f_accuracy():
 
 def test_sampler_tables():
     inv, fc = oracle.sampler_tables()
-    k = np.arange(1, 128)
-    assert len(inv) == 128 and inv[0] == 0
+    k = np.arange(1, 256)
+    assert len(inv) == 256 and inv[0] == 0
     assert np.array_equal(inv[1:], (np.float32(1.0) / k.astype(np.float32)))
     from math import lgamma, log, pi
     for j in range(10):

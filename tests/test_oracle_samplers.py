@@ -76,8 +76,10 @@ def test_poisson_zero_consumes_nothing():
 @pytest.mark.parametrize("n,p", [(5, 0.3), (40, 0.2), (25, 0.41), (100, 0.099), (100, 0.1), (30, 0.34),
                                  (100, 0.5), (7, 0.5), (1000, 0.02), (10000, 0.005), (37, 0.9),
                                  (5000, 0.75), (2, 0.99), (100000, 0.3), (3000, 0.0034),
-                                 # around the inversion / BTRS switch at n p = 40
-                                 (400, 0.0999), (400, 0.1), (80, 0.49), (200, 0.2), (1000, 0.035), (60, 0.55)])
+                                 (400, 0.0999), (400, 0.1), (80, 0.49), (200, 0.2), (1000, 0.035), (60, 0.55),
+                                 # around the inversion / BTRS switch at n p = 56
+                                 (560, 0.0999), (560, 0.1), (114, 0.49), (115, 0.49), (1600, 0.035), (500, 0.112),
+                                 (130, 0.43), (150, 0.627), (152, 0.63)])
 def test_binomial(n, p):
     N = 300000
     s = oracle.sample(oracle.SMP_BINOMIAL, N, seed=23, i0=n, f0=p)
