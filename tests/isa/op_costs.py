@@ -63,7 +63,7 @@ def event_costs(p: dict) -> dict:
         # Philox4x32-10 block; one uniform: the conversion
         "philox": p["philox"],
         "uniform": p["unit"],
-        # every binomial draw: n <= 0, n p < 40 (cvt, mul, cmp), the flip n - k
+        # every binomial draw: n <= 0, n p < 56 (cvt, mul, cmp), the flip n - k
         "binomial_call": 5,
         # inversion: g = r (n + 1), f0 = e^{n lq}, kmax, go;  step: f (g / k - r), F + f, k, two tests
         "bin_inv": 3 + 1 + p["ex"] + 1 + 2,
