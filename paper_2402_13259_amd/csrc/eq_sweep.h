@@ -206,28 +206,73 @@ __device__ __forceinline__ void finish_task(const NetView &v, int s, int t, unsi
   if (v.tsums && v.K > 0) add_tile_stats(v, s, t, x, q, 0, lane);
 }
 
+// The network's read-only tables, passed again as kernel parameters of their own: marked
+// __restrict__ (nothing writes them during a launch), their loads at wavefront-uniform
+// addresses -- a station's records, each routing edge, the target's inflow ring, the step's
+// arrival integral -- become scalar loads instead of vector loads of one address (4 % on the
+// 1000-station step).  A pointer read from the argument struct carries no such guarantee.
+struct Tables {
+  const StationParam *sp;
+  const BinomP *dep;
+  const int *heavy;
+  const StationRing *sp2;
+  const Edge *edges;
+  const float *g;
+  const int *segidx, *seg_m;
+  const float *seg_rate;
+  const ScoreParam *scp;
+};
+#define EQ_TABLE_PARAMS                                                                              \
+  const StationParam *__restrict__ t_sp, const BinomP *__restrict__ t_dep, const int *__restrict__ t_heavy, \
+      const StationRing *__restrict__ t_sp2, const Edge *__restrict__ t_edges, const float *__restrict__ t_g, \
+      const int *__restrict__ t_segidx, const int *__restrict__ t_seg_m, const float *__restrict__ t_seg_rate, \
+      const ScoreParam *__restrict__ t_scp
+
+__device__ __forceinline__ NetView bind_tables(NetView v, const StationParam *sp, const BinomP *dep, const int *heavy,
+                                               const StationRing *sp2, const Edge *edges, const float *g,
+                                               const int *segidx, const int *seg_m, const float *seg_rate,
+                                               const ScoreParam *scp) {
+  v.sp = sp; v.dep = dep; v.heavy = heavy; v.sp2 = sp2; v.edges = edges; v.g = g;
+  v.segidx = segidx; v.seg_m = seg_m; v.seg_rate = seg_rate; v.scp = scp;
+  return v;
+}
+#define EQ_BIND_TABLES(view) \
+  bind_tables(view, t_sp, t_dep, t_heavy, t_sp2, t_edges, t_g, t_segidx, t_seg_m, t_seg_rate, t_scp)
+
+inline Tables tables_of(const NetView &v) {
+  return Tables{v.sp, v.dep, v.heavy, v.sp2, v.edges, v.g, v.segidx, v.seg_m, v.seg_rate, v.scp};
+}
+#define EQ_TABLE_ARGS(t) t.sp, t.dep, t.heavy, t.sp2, t.edges, t.g, t.segidx, t.seg_m, t.seg_rate, t.scp
+
 template <int SCHEME, bool SCORE, bool REC>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs a, EQ_TABLE_PARAMS) {
+  const NetView v = EQ_BIND_TABLES(a.v);
   TaskPos tp;
-  if (!task_of(a.v, tp)) return;
-  const int lag = SCHEME == 0 ? 0 : uniform(a.v.sp2[tp.s].lag);
+  if (!task_of(v, tp)) return;
+  const int lag = SCHEME == 0 ? 0 : uniform(v.sp2[tp.s].lag);
   const int tau = a.iter - lag;          // launches are numbered from 1
-  if (tau < 1 || tau > a.v.K) return;
-  sweep_task<SCHEME, SCORE, REC>(a.v, tp.s, tp.t, tau, a.dep_mode, a.dt, a.flags);
+  if (tau < 1 || tau > v.K) return;
+  sweep_task<SCHEME, SCORE, REC>(v, tp.s, tp.t, tau, a.dep_mode, a.dt, a.flags);
 }
 
 template <bool SCORE, bool REC>
-__global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs a) {
+__global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs a, EQ_TABLE_PARAMS) {
+  const NetView v = EQ_BIND_TABLES(a.v);
   TaskPos tp;
-  if (!task_of(a.v, tp)) return;
-  finish_task<SCORE, REC>(a.v, tp.s, tp.t, a.flags);
+  if (!task_of(v, tp)) return;
+  finish_task<SCORE, REC>(v, tp.s, tp.t, a.flags);
 }
 
 // Average scheme: the backward and the forward scheme of one network advance in the same
 // launch (common random numbers come from the shared counters).  Within a tile's group the
 // tasks alternate backward / forward over the stations, heaviest first; backward tasks run
 // step iter, forward tasks step iter - level.
-__global__ __launch_bounds__(256) void k_sweep_pair(PairArgs a) {
+__global__ __launch_bounds__(256) void k_sweep_pair(PairArgs a, EQ_TABLE_PARAMS,
+                                                    const StationRing *__restrict__ t_sp2f) {
+  // both views read the same network's tables but their own inflow rings (t_sp2: backward)
+  a.vb = EQ_BIND_TABLES(a.vb);
+  a.vf = EQ_BIND_TABLES(a.vf);
+  a.vf.sp2 = t_sp2f;
   const int b = blockIdx.x, wave = threadIdx.x >> 6;
   const int xcd = b & 7, local = b >> 3;
   const int tl = uniform(local * (int)(blockDim.x >> 6) + wave);
@@ -306,25 +351,27 @@ hipError_t launch_sweep_init(int *N, const int *init, long long nstate, int *rin
 }
 
 hipError_t launch_sweep(const SweepArgs &a, int scheme, int mode, int wpb, hipStream_t st) {
+  const Tables t = tables_of(a.v);
   const int grid = sweep_grid(a.v, wpb);
   const dim3 blk(64 * wpb);
   if (scheme == 0) {
-    if (mode == 1) hipLaunchKernelGGL((k_sweep<0, true, false>), dim3(grid), blk, 0, st, a);
-    else if (mode == 2) hipLaunchKernelGGL((k_sweep<0, false, true>), dim3(grid), blk, 0, st, a);
-    else hipLaunchKernelGGL((k_sweep<0, false, false>), dim3(grid), blk, 0, st, a);
+    if (mode == 1) hipLaunchKernelGGL((k_sweep<0, true, false>), dim3(grid), blk, 0, st, a, EQ_TABLE_ARGS(t));
+    else if (mode == 2) hipLaunchKernelGGL((k_sweep<0, false, true>), dim3(grid), blk, 0, st, a, EQ_TABLE_ARGS(t));
+    else hipLaunchKernelGGL((k_sweep<0, false, false>), dim3(grid), blk, 0, st, a, EQ_TABLE_ARGS(t));
   } else {
-    if (mode == 1) hipLaunchKernelGGL((k_sweep<1, true, false>), dim3(grid), blk, 0, st, a);
-    else if (mode == 2) hipLaunchKernelGGL((k_sweep<1, false, true>), dim3(grid), blk, 0, st, a);
-    else hipLaunchKernelGGL((k_sweep<1, false, false>), dim3(grid), blk, 0, st, a);
+    if (mode == 1) hipLaunchKernelGGL((k_sweep<1, true, false>), dim3(grid), blk, 0, st, a, EQ_TABLE_ARGS(t));
+    else if (mode == 2) hipLaunchKernelGGL((k_sweep<1, false, true>), dim3(grid), blk, 0, st, a, EQ_TABLE_ARGS(t));
+    else hipLaunchKernelGGL((k_sweep<1, false, false>), dim3(grid), blk, 0, st, a, EQ_TABLE_ARGS(t));
   }
   return hipGetLastError();
 }
 
 hipError_t launch_sweep_finish(const SweepArgs &a, int mode, int wpb, hipStream_t st) {
+  const Tables t = tables_of(a.v);
   const dim3 blk(64 * wpb), grid(sweep_grid(a.v, wpb));
-  if (mode == 1) hipLaunchKernelGGL((k_sweep_finish<true, false>), grid, blk, 0, st, a);
-  else if (mode == 2) hipLaunchKernelGGL((k_sweep_finish<false, true>), grid, blk, 0, st, a);
-  else hipLaunchKernelGGL((k_sweep_finish<false, false>), grid, blk, 0, st, a);
+  if (mode == 1) hipLaunchKernelGGL((k_sweep_finish<true, false>), grid, blk, 0, st, a, EQ_TABLE_ARGS(t));
+  else if (mode == 2) hipLaunchKernelGGL((k_sweep_finish<false, true>), grid, blk, 0, st, a, EQ_TABLE_ARGS(t));
+  else hipLaunchKernelGGL((k_sweep_finish<false, false>), grid, blk, 0, st, a, EQ_TABLE_ARGS(t));
   return hipGetLastError();
 }
 
@@ -369,7 +416,8 @@ hipError_t launch_sweep_pair(const PairArgs &a, int wpb, hipStream_t st) {
   const int per_xcd_tiles = (a.vb.tiles + 7) / 8;
   const int tasks_per_xcd = per_xcd_tiles * 2 * a.vb.n;
   const int grid = 8 * ((tasks_per_xcd + wpb - 1) / wpb);
-  hipLaunchKernelGGL(k_sweep_pair, dim3(grid), dim3(64 * wpb), 0, st, a);
+  const Tables t = tables_of(a.vb);
+  hipLaunchKernelGGL(k_sweep_pair, dim3(grid), dim3(64 * wpb), 0, st, a, EQ_TABLE_ARGS(t), a.vf.sp2);
   return hipGetLastError();
 }
 
