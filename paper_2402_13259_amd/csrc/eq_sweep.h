@@ -312,7 +312,11 @@ template <int SCHEME>
 __global__ __launch_bounds__(1024) void k_batch_step(BatchArgs a) {
   int k, s, t;
   if (!batch_task(a, k, s, t)) return;
-  const NetView &v = a.nets[k].v;
+  // A copy, read once at the start (before the task stores anything): the fields and the
+  // table records read through them at wavefront-uniform addresses become scalar loads; through
+  // a reference the compiler reloads them after every store, with vector loads (8 % of the
+  // batch step).
+  const NetView v = a.nets[k].v;
   const int lag = SCHEME == 0 ? 0 : uniform(v.sp2[s].lag);
   const int tau = a.iter - lag;
   if (tau < 1 || tau > v.K) return;
@@ -322,7 +326,8 @@ __global__ __launch_bounds__(1024) void k_batch_step(BatchArgs a) {
 __global__ __launch_bounds__(1024) void k_batch_finish(BatchArgs a) {
   int k, s, t;
   if (!batch_task(a, k, s, t)) return;
-  finish_task<false, false>(a.nets[k].v, s, t, a.flags);
+  const NetView v = a.nets[k].v;
+  finish_task<false, false>(v, s, t, a.flags);
 }
 
 // N = init (or 0), inflow slots = 0, tile sums = 0.
