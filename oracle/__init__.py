@@ -98,6 +98,10 @@ def _load(path: str):
     L.orc_sojourn.argtypes = [C.POINTER(_Net), i32, u64, u32, i32, vp, i32, i32, vp, vp, vp, i32, vp, vp, vp]
     L.orc_lemma3.argtypes = [i32, i32, i32]
     L.orc_lemma3.restype = f32
+    L.orc_btrs_log_ratio.argtypes = [i32, f32, i32]
+    L.orc_btrs_log_ratio.restype = f32
+    L.orc_ptrs_log_pmf.argtypes = [f32, i32]
+    L.orc_ptrs_log_pmf.restype = f32
     L.orc_sample.argtypes = [i32, i64, u64, u32, u32, u32, u32, i32, i32, f32, f32, f32, f32, vp]
     L.orc_math.argtypes = [i32, i64, vp, vp]
     L.orc_philox_batch.argtypes = [i64, vp, vp, vp]
@@ -220,6 +224,17 @@ def sojourn(net, scheme: int, seed: int, rec: dict, i0: Sequence[int], tau0: Seq
 
 def lemma3(x: int, d: int, m: int) -> float:
     return float(lib().orc_lemma3(int(x), int(d), int(m)))
+
+
+def btrs_log_ratio(n: int, p: float, k: int) -> float:
+    """BTRS's acceptance log-ratio ln f(k)/f(m) of Binomial(n, p), 0 < p <= 1/2, m = floor((n+1) p),
+    as the sampler computes it (Stirling series, fp32)."""
+    return float(lib().orc_btrs_log_ratio(int(n), C.c_float(p), int(k)))
+
+
+def ptrs_log_pmf(lam: float, k: int) -> float:
+    """PTRS's acceptance bound ln f(k) of Poisson(lam), as the sampler computes it (Stirling series, fp32)."""
+    return float(lib().orc_ptrs_log_pmf(C.c_float(lam), int(k)))
 
 
 def tables(net, dt: float, K: int) -> dict:

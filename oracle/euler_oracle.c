@@ -348,6 +348,22 @@ float orc_stirling_fc(int32_t j)
 /* ------------------------------------------------------------------------- */
 #define REJECT_CAP 100000
 
+/* ln f(k) = k ln lam - lam - ln k! of Poisson(lam), with ln k! by the Stirling series:   */
+/*   (k+1-lam) - (k+1/2) log1p((k+1-lam)/lam) - ln(lam)/2 - ln(2pi)/2 - fc(k).               */
+/* loglam = ln(lam) as the caller made it.  PTRS's acceptance test compares against this. */
+static float ptrs_log_pmf(float lam, float loglam, float kf)
+{
+    float t = (kf + 1.0f) - lam;
+    return t - (kf + 0.5f) * orc_log1pf(t / lam) - 0.5f * loglam - HALF_LOG_2PI - orc_stirling_fc((int32_t)kf);
+}
+
+/* The same, exported for its pin against lgamma. */
+float orc_ptrs_log_pmf(float lam, int32_t k)
+{
+    pthread_once(&tab_once, init_tables);
+    return ptrs_log_pmf(lam, orc_logf(lam), (float)k);
+}
+
 /* Poisson(lam).  lam < 10: sequential-search inversion from k = 0 (one uniform). */
 /* lam >= 10: PTRS transformed rejection with squeeze (Hormann 1993).             */
 int32_t orc_poisson(float lam, ustream *S)
@@ -388,13 +404,8 @@ int32_t orc_poisson(float lam, ustream *S)
         if (us >= 0.07f && V <= vr) return (int32_t)kf;
         if (kf < 0.0f || (us < 0.013f && V > us)) continue;
         EV(EV_PTRS_SLOW);
-        /* ln f(k) = k ln lam - lam - ln k!, with ln k! by the Stirling series:      */
-        /*   = (k+1-lam) - (k+1/2) log1p((k+1-lam)/lam) - ln(lam)/2 - ln(2pi)/2 - fc(k) */
         float lhs = orc_logf(V * invalpha / (a / (us * us) + b));
-        float t = (kf + 1.0f) - lam;
-        float rhs = t - (kf + 0.5f) * orc_log1pf(t / lam) - 0.5f * loglam - HALF_LOG_2PI
-                    - orc_stirling_fc((int32_t)kf);
-        if (lhs <= rhs) return (int32_t)kf;
+        if (lhs <= ptrs_log_pmf(lam, loglam, kf)) return (int32_t)kf;
     }
     if (S->overflow) *S->overflow = 1;
     return (int32_t)floorf(lam);
@@ -424,6 +435,40 @@ static int32_t binom_inversion(int32_t n, float p, ustream *S)
     return k;
 }
 
+/* ln f(k)/f(m) of Binomial(n, p), r = p/q, m = mf = floor((n+1) p), by the Stirling series:  */
+/*   hm + (n+1) ln(nm/nk) + (k+1/2) ln(nk r/(k+1)) - fc(k) - fc(n-k),  nm = n-m+1, nk = n-k+1, */
+/*   hm = (m+1/2) ln((m+1)/(r nm)) + fc(m) + fc(n-m),                                           */
+/* with ln(nm/nk) = log1p((k-m)/nk).  ln((m+1)/(r nm)) is log1p((m + 1 - r nm) / (r nm)): for */
+/* a large mode the ratio is near 1, and rounding it before the log, times m + 1/2, would    */
+/* swamp the log-ratio; so the difference is one fp64 fma of exact integers (n - m + 1 and   */
+/* m + 1 below 2^28, times the fp32 r: an exact product), rounded once (likewise ln(nk r/(k+1))). */
+static float btrs_hm(int32_t n, float nf, int32_t m, float mf, float r)
+{
+    float nm = nf - mf + 1.0f;
+    float rnm = r * nm;
+    float dm = (float)fma(-(double)r, (double)(n - m + 1), (double)(m + 1));
+    return (mf + 0.5f) * orc_log1pf(dm / rnm) + orc_stirling_fc(m) + orc_stirling_fc(n - m);
+}
+
+static float btrs_log_ratio(float hm, int32_t n, float nf, float mf, float r, int32_t k, float kf)
+{
+    float nk = nf - kf + 1.0f;
+    return hm + (nf + 1.0f) * orc_log1pf((kf - mf) / nk)
+           + (kf + 0.5f) * orc_log1pf((float)fma((double)r, (double)(n - k + 1), -(double)(k + 1)) / (kf + 1.0f))
+           - orc_stirling_fc(k) - orc_stirling_fc(n - k);
+}
+
+/* The same for 0 < p <= 1/2, exported for its pin against lgamma. */
+float orc_btrs_log_ratio(int32_t n, float p, int32_t k)
+{
+    pthread_once(&tab_once, init_tables);
+    float nf = (float)n;
+    float r = p / (1.0f - p);
+    float mf = floorf((nf + 1.0f) * p);
+    int32_t m = (int32_t)mf;
+    return btrs_log_ratio(btrs_hm(n, nf, m, mf, r), n, nf, mf, r, k, (float)k);
+}
+
 /* Binomial(n, p) for n*p >= 56, p <= 1/2: transformed rejection with squeeze */
 /* (BTRS of Hormann 1993).  Acceptance compares against ln f(k)/f(m), m the mode. */
 static int32_t binom_btrs(int32_t n, float p, ustream *S)
@@ -440,14 +485,7 @@ static int32_t binom_btrs(int32_t n, float p, ustream *S)
     float r = p / q;
     float mf = floorf((nf + 1.0f) * p);
     int32_t m = (int32_t)mf;
-    float nm = nf - mf + 1.0f;
-    /* ln((m+1)/(r nm)) as log1p((m + 1 - r nm) / (r nm)).  For a large mode the ratio is    */
-    /* near 1, and rounding it before the log, times m + 1/2, would swamp the log-ratio; so  */
-    /* the difference is one fp64 fma of exact integers (n - m + 1 and m + 1 below 2^28,     */
-    /* times the fp32 r: exact product), rounded once (likewise ln(nk r/(k+1)) below).      */
-    float rnm = r * nm;
-    float dm = (float)fma(-(double)r, (double)(n - m + 1), (double)(m + 1));
-    float hm = (mf + 0.5f) * orc_log1pf(dm / rnm) + orc_stirling_fc(m) + orc_stirling_fc(n - m);
+    float hm = btrs_hm(n, nf, m, mf, r);
     /* a mode of 2^24 or more: fp32 cannot represent the values exactly (overflow flag) */
     if (m >= (1 << 24) && S->overflow) *S->overflow = 1;
     EV(EV_BTRS);
@@ -463,13 +501,7 @@ static int32_t binom_btrs(int32_t n, float p, ustream *S)
         if (k > n) continue;               /* nf may round n up when n >= 2^24 */
         EV(EV_BTRS_SLOW);
         float lhs = orc_logf(v * alpha / (a / (us * us) + b));
-        float nk = nf - kf + 1.0f;
-        /* ln f(k)/f(m) by the Stirling series; ln(nm/nk) = log1p((k-m)/nk). */
-        float rhs = hm + (nf + 1.0f) * orc_log1pf((kf - mf) / nk)
-                    + (kf + 0.5f) * orc_log1pf((float)fma((double)r, (double)(n - k + 1), -(double)(k + 1))
-                                              / (kf + 1.0f))
-                    - orc_stirling_fc(k) - orc_stirling_fc(n - k);
-        if (lhs <= rhs) return k;
+        if (lhs <= btrs_log_ratio(hm, n, nf, mf, r, k, kf)) return k;
     }
     if (S->overflow) *S->overflow = 1;
     return m;

@@ -90,6 +90,54 @@ def test_binomial(n, p):
     assert abs(s.mean() - m) < 5 * math.sqrt(m * (1 - float(np.float32(p))) / N) + 1e-9
 
 
+def _stirling_terms(j):
+    """fc(j) = ln j! - ((j + 1/2) ln(j + 1) - (j + 1) + ln(2 pi)/2), fp64 from lgamma."""
+    return math.lgamma(j + 1) - ((j + 0.5) * math.log(j + 1) - (j + 1) + 0.5 * math.log(2 * math.pi))
+
+
+@pytest.mark.parametrize("n,p", [(115, 0.49), (130, 0.43), (200, 0.3), (1000, 0.2), (5000, 0.0125), (100000, 0.37),
+                                 (10_000_000, 0.1), (134_000_001, 0.12)])
+def test_btrs_log_ratio_against_lgamma(n, p):
+    """BTRS accepts against ln f(k)/f(m), m = floor((n+1) p), which it evaluates by Stirling's
+    series in log1p form.  Here that value is checked against ln f(k)/f(m) from lgamma in fp64,
+    for k within 6 standard deviations of the mode, to the rounding the fp32 evaluation allows
+    (a few ulp of its largest term).  A dropped or flipped Stirling remainder, or a wrong
+    coefficient of a log term, moves it far beyond that (3e-3 and more at n = 115)."""
+    p32 = np.float32(p)
+    pf, qf = float(p32), 1.0 - float(p32)
+    m = int(np.floor((np.float32(n) + np.float32(1.0)) * p32))
+    sd = math.sqrt(n * pf * qf)
+    ks = np.unique(np.clip(np.round(m + np.linspace(-6, 6, 49) * sd), 0, n).astype(np.int64))
+    lr = math.log(pf / qf)
+    for k in ks:
+        k = int(k)
+        exact = (math.lgamma(m + 1) + math.lgamma(n - m + 1) - math.lgamma(k + 1) - math.lgamma(n - k + 1)
+                 + (k - m) * lr)
+        got = oracle.btrs_log_ratio(n, pf, k)
+        nk = n - k + 1
+        scale = (abs((m + 0.5) * math.log1p((m + 1 - (pf / qf) * (n - m + 1)) / ((pf / qf) * (n - m + 1))))
+                 + (n + 1) * abs(math.log1p((k - m) / nk)) + (k + 0.5) * abs(math.log((pf / qf) * nk / (k + 1)))
+                 + 1.0)
+        assert abs(got - exact) <= 16 * 2.0 ** -24 * scale, (n, p, k, got, exact, scale)
+
+
+@pytest.mark.parametrize("lam", [10.0, 37.2, 250.0, 4000.5, 1.0e6, 1.6e7])
+def test_ptrs_log_pmf_against_lgamma(lam):
+    """PTRS accepts against ln f(k) = k ln lam - lam - ln k!, which it evaluates by Stirling's series
+    in log1p form; checked against lgamma in fp64 for k within 6 standard deviations, to the
+    rounding of the fp32 evaluation (a few ulp of its largest term)."""
+    l32 = float(np.float32(lam))
+    sd = math.sqrt(l32)
+    ks = np.unique(np.clip(np.round(l32 + np.linspace(-6, 6, 49) * sd), 0, None).astype(np.int64))
+    for k in ks:
+        k = int(k)
+        exact = k * math.log(l32) - l32 - math.lgamma(k + 1)
+        got = oracle.ptrs_log_pmf(l32, k)
+        t = k + 1 - l32
+        scale = abs(t) + (k + 0.5) * abs(math.log1p(t / l32)) + 0.5 * abs(math.log(l32)) + 2.0
+        assert abs(got - exact) <= 16 * 2.0 ** -24 * scale, (lam, k, got, exact, scale)
+
+
 def test_binomial_degenerate():
     assert np.all(oracle.sample(oracle.SMP_BINOMIAL, 50, i0=0, f0=0.5) == 0)
     assert np.all(oracle.sample(oracle.SMP_BINOMIAL, 50, i0=9, f0=0.0) == 0)
