@@ -88,7 +88,7 @@ enum {
     EV_PTRS,           /* Poisson draws by PTRS */
     EV_PTRS_TRY,       /*   attempts */
     EV_PTRS_SLOW,      /*   attempts that reach the logarithmic test */
-    EV_BIN_INV,        /* binomial draws by inversion (n p < 56) */
+    EV_BIN_INV,        /* binomial draws by inversion (n p < 80) */
     EV_BIN_INV_STEP,   /*   their search steps */
     EV_BTRS,           /* binomial draws by BTRS */
     EV_BTRS_TRY,       /*   attempts */
@@ -305,8 +305,8 @@ float orc_expm1f(float x)
 /* ------------------------------------------------------------------------- */
 #define INV_TAB 256
 #define POIS_INV_MAX 63          /* Poisson inversion (lam < 10) stops at k = 63 */
-#define BINOM_INV_MAX 255        /* binomial inversion (n p < 56) stops at k = 255 */
-#define BINOM_INV_NP 56.0f       /* n p below this: inversion, else BTRS */
+#define BINOM_INV_MAX 255        /* binomial inversion (n p < 80) stops at k = 255 */
+#define BINOM_INV_NP 80.0f       /* n p below this: inversion, else BTRS */
 static float INV[INV_TAB];
 static float FC_TAB[10];
 static pthread_once_t tab_once = PTHREAD_ONCE_INIT;
@@ -411,17 +411,28 @@ int32_t orc_poisson(float lam, ustream *S)
     return (int32_t)floorf(lam);
 }
 
-/* Binomial(n, p) for n*p < 56, 0 < p <= 1/2: inversion from k = 0 (one uniform),  */
-/* at most BINOM_INV_MAX steps (P(X > 255) < 1e-60 there).  q^n >= e^-78 stays a     */
-/* normal fp32 number (n ln(1/q) <= 2 ln 2 n p for p <= 1/2).                        */
+/* Binomial(n, p) for n*p < 80, 0 < p <= 1/2: inversion from k = 0 (one uniform),  */
+/* at most BINOM_INV_MAX steps (P(X > 255) < 1e-40 there).                           */
+/* P(X = 0) = q^n = e^x, x = n ln q >= -2 ln 2 n p > -111, is formed as the          */
+/* exponential forms it, exp(r) 2^e with x = e ln 2 + r, but with the binary exponent */
+/* raised by sc = -120 - e when e < -120 (q^n below the normal fp32 range), and the  */
+/* uniform raised by the same 2^sc.  Scaling by a power of two is exact, so every    */
+/* step and comparison is the one an fp32 without the lower exponent limit makes;    */
+/* sc = 0 for n p < 56, where q^n >= e^-78 is a normal number anyway.                */
 static int32_t binom_inversion(int32_t n, float p, ustream *S)
 {
     float q = 1.0f - p;
     float r = p / q;
     float g = r * ((float)n + 1.0f);
-    float f = orc_expf((float)n * orc_log1pf(-p));   /* P(X = 0) = q^n */
+    float x = (float)n * orc_log1pf(-p);
+    float ek = rintf(x * INV_LN2);
+    float rr = fmaf(-ek, LN2_HI, x);
+    rr = fmaf(-ek, LN2_LO, rr);
+    int32_t e = (int32_t)ek;
+    int32_t sc = e < -120 ? -120 - e : 0;
+    float f = exp_poly(rr) * f_from_bits((uint32_t)(e + sc + 127) << 23);   /* P(X = 0) 2^sc */
     float F = f;
-    float u = us_u01(S);
+    float u = us_u01(S) * f_from_bits((uint32_t)(sc + 127) << 23);
     int32_t k = 0;
     EV(EV_BIN_INV);
     while (u > F && k < n && k < BINOM_INV_MAX) {
@@ -469,7 +480,7 @@ float orc_btrs_log_ratio(int32_t n, float p, int32_t k)
     return btrs_log_ratio(btrs_hm(n, nf, m, mf, r), n, nf, mf, r, k, (float)k);
 }
 
-/* Binomial(n, p) for n*p >= 56, p <= 1/2: transformed rejection with squeeze */
+/* Binomial(n, p) for n*p >= 80, p <= 1/2: transformed rejection with squeeze */
 /* (BTRS of Hormann 1993).  Acceptance compares against ln f(k)/f(m), m the mode. */
 static int32_t binom_btrs(int32_t n, float p, ustream *S)
 {

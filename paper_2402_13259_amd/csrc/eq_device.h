@@ -203,12 +203,12 @@ __device__ __forceinline__ float rate_in(const int *segidx, const float *seg_rat
 // ------------------------------------------------------------------------------------
 constexpr int kRcpTab = 256;
 constexpr int kPoisInvMax = 63;      // Poisson inversion (lam < 10) stops at k = 63
-constexpr int kBinomInvMax = 255;    // binomial inversion (n p < 56) stops at k = 255
+constexpr int kBinomInvMax = 255;    // binomial inversion (n p < 80) stops at k = 255
 // n p below this: inversion, else BTRS.  Both are exact samplers; the switch sits where a
 // wavefront's cost of the two meets: inversion runs to its slowest lane's k, about n p +
 // 2.4 sqrt(n p) steps over 64 lanes, and BTRS to its slowest lane's attempt, with the
 // logarithmic test taken in nearly every attempt by some lane.
-constexpr float kBinomInvNp = 56.0f;
+constexpr float kBinomInvNp = 80.0f;
 extern __constant__ float4 c_rcp4[kRcpTab / 4];
 extern __constant__ float c_fc[10];
 
@@ -273,16 +273,26 @@ __device__ __forceinline__ int poisson(float lam, Stream &S, uint32_t &flags) {
   return (int)__builtin_floorf(lam);
 }
 
-// Binomial(n, p), n p < 56, 0 < p <= 1/2: inversion from 0 with the pmf recurrence
-// f_k = f_{k-1} ((n+1) r / k - r), r = p/q, f_0 = e^{n lq} >= e^-78 (a normal fp32 number),
-// lq = ln(1 - p), at most 255 steps (P(X > 255) < 1e-60).  Every lane still searching
+// Binomial(n, p), n p < 80, 0 < p <= 1/2: inversion from 0 with the pmf recurrence
+// f_k = f_{k-1} ((n+1) r / k - r), r = p/q, f_0 = e^{n lq}, lq = ln(1 - p), at most 255 steps
+// (P(X > 255) < 1e-40).  f_0 is formed as ex() forms it, exp(r) 2^e with n lq = e ln 2 + r, but
+// with the binary exponent raised by sc = -120 - e when e < -120 (f_0 below the normal fp32
+// range; n lq > -111 here), and the uniform raised by the same 2^sc: scaling by a power of two is
+// exact, so every step and comparison is the one an fp32 without the lower exponent limit
+// makes (sc = 0 for n p < 56, where f_0 >= e^-78 is normal anyway).  Every lane still searching
 // is at the same k, so a pass takes four steps with one scalar load of their four
 // reciprocals; a lane stops at exactly the step the one-step search stops at.
 __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, uint32_t &flags) {
   const float g = r * ((float)n + 1.0f);
-  float f = ex((float)n * lq);
+  const float x = (float)n * lq;
+  const float ek = __builtin_rintf(x * INV_LN2);
+  float rr = fma32(-ek, LN2_HI, x);
+  rr = fma32(-ek, LN2_LO, rr);
+  const int e = (int)ek;
+  const int sc = e < -120 ? -120 - e : 0;
+  float f = exp_small(rr) * __uint_as_float((uint32_t)(e + sc + 127) << 23);   // P(X = 0) 2^sc
   float F = f;
-  const float u = draw_unit(S, flags);
+  const float u = draw_unit(S, flags) * __uint_as_float((uint32_t)(sc + 127) << 23);
   const int kmax = n < kBinomInvMax ? n : kBinomInvMax;
   int k = 0;
   bool go = u > F && 0 < kmax;
@@ -319,7 +329,7 @@ __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, ui
   return k;
 }
 
-// Binomial(n, p), n p >= 56, p <= 1/2: BTRS (Hormann 1993), acceptance against
+// Binomial(n, p), n p >= 80, p <= 1/2: BTRS (Hormann 1993), acceptance against
 // ln f(k)/f(mode) from Stirling's series.
 __device__ __forceinline__ int binom_btrs(int n, float p, float r, Stream &S, uint32_t &flags) {
   const float nf = (float)n;

@@ -63,10 +63,11 @@ def event_costs(p: dict) -> dict:
         # Philox4x32-10 block; one uniform: the conversion
         "philox": p["philox"],
         "uniform": p["unit"],
-        # every binomial draw: n <= 0, n p < 56 (cvt, mul, cmp), the flip n - k
+        # every binomial draw: n <= 0, n p < 80 (cvt, mul, cmp), the flip n - k
         "binomial_call": 5,
-        # inversion: g = r (n + 1), f0 = e^{n lq}, kmax, go;  step: f (g / k - r), F + f, k, two tests
-        "bin_inv": 3 + 1 + p["ex"] + 1 + 2,
+        # inversion: g = r (n + 1), f0 = e^{n lq} (the exponential's steps, with the exponent scale:
+        # its test, the offset, the uniform's factor), kmax, go;  step: f (g / k - r), F + f, k, two tests
+        "bin_inv": 3 + 1 + p["ex"] + 4 + 1 + 2,
         "bin_inv_step": 7,
         # BTRS set-up (spq, b, a, c, alpha, vr, mode, nm, the mode's log-ratio and Stirling terms)
         "btrs": 30 + p["sqrt"] + 3 * p["div"] + p["floor"] + p["fma64"] + L1P + 2 * ST,

@@ -92,6 +92,7 @@ SAMPLER_CASES = [
     (1, dict(i0=7, f0=0.2)), (1, dict(i0=40, f0=0.3)), (1, dict(i0=1000, f0=0.01)), (1, dict(i0=9000, f0=0.0049)),
     (1, dict(i0=60, f0=0.8)), (1, dict(i0=100000, f0=0.37)), (1, dict(i0=5, f0=1.0)),
     (1, dict(i0=560, f0=0.0999)), (1, dict(i0=560, f0=0.1)), (1, dict(i0=114, f0=0.49)),
+    (1, dict(i0=158, f0=0.5)), (1, dict(i0=400, f0=0.19)), (1, dict(i0=800, f0=0.0999)), (1, dict(i0=800, f0=0.1)),
     (2, dict(i0=1)), (2, dict(i0=3)), (2, dict(i0=50)), (2, dict(i0=20000)),
     (3, dict(i0=5, i1=10, f0=1.0, f1=0.5)), (3, dict(i0=30, i1=10, f0=1.0, f1=0.05)),
     (3, dict(i0=40, i1=20, f0=3.0, f1=0.5)), (3, dict(i0=9000, i1=8000, f0=1.1, f1=0.005)),

@@ -41,8 +41,9 @@ def sampler_checks():
     return {
         "poisson_inversion": lambda: ts.test_poisson(3.3),
         "poisson_ptrs": lambda: ts.test_poisson(37.2),
-        "binomial_inversion": lambda: [ts.test_binomial(n, p) for n, p in ((40, 0.2), (560, 0.0999), (150, 0.627))],
-        "binomial_btrs": lambda: [ts.test_binomial(n, p) for n, p in ((1000, 0.2), (560, 0.1), (5000, 0.75))],
+        "binomial_inversion": lambda: [ts.test_binomial(n, p) for n, p in ((40, 0.2), (560, 0.0999), (150, 0.627),
+                                                                        (158, 0.5), (400, 0.19))],
+        "binomial_btrs": lambda: [ts.test_binomial(n, p) for n, p in ((1000, 0.2), (800, 0.1), (5000, 0.75))],
         "gamma": lambda: [ts.test_gamma(k) for k in (5, 30)],
         "gendep": lambda: [ts.test_generate_departure_exact_law(*c) for c in
                            ((5, 10, 1.0, 0.5), (12, 12, 1.0, 0.1), (13, 12, 1.5, 0.2), (30, 10, 1.0, 0.05),
@@ -85,8 +86,9 @@ MUTANTS = {
     "poisson_inversion_index": ([("p = p * (lam * INV[k]);", "p = p * (lam * INV[k + 1]);")], "sampler"),
     "ptrs_log_sign": ([("- 0.5f * loglam - HALF_LOG_2PI", "+ 0.5f * loglam - HALF_LOG_2PI")], "sampler"),
     "binomial_recurrence_sign": ([("f = f * (g * INV[k] - r);", "f = f * (g * INV[k] + r);")], "sampler"),
-    "binomial_start": ([("float f = orc_expf((float)n * orc_log1pf(-p));", "float f = orc_expf(-(float)n * p);")],
-                       "sampler"),
+    "binomial_start": ([("float x = (float)n * orc_log1pf(-p);", "float x = -(float)n * p;")], "sampler"),
+    "binomial_unscaled_uniform": ([("float u = us_u01(S) * f_from_bits((uint32_t)(sc + 127) << 23);",
+                                    "float u = us_u01(S);")], "sampler"),
     "btrs_tail_sign": ([(BTRS_TAIL, "- orc_stirling_fc(k) + orc_stirling_fc(n - k);")], "sampler"),
     "btrs_mode_term": ([("(mf + 0.5f) * orc_log1pf(dm / rnm)", "(mf - 0.5f) * orc_log1pf(dm / rnm)")], "sampler"),
     "btrs_switch_flip": ([("return n - k;\n    }", "return k;\n    }")], "sampler"),

@@ -77,9 +77,12 @@ def test_poisson_zero_consumes_nothing():
                                  (100, 0.5), (7, 0.5), (1000, 0.02), (10000, 0.005), (37, 0.9),
                                  (5000, 0.75), (2, 0.99), (100000, 0.3), (3000, 0.0034),
                                  (400, 0.0999), (400, 0.1), (80, 0.49), (200, 0.2), (1000, 0.035), (60, 0.55),
-                                 # around the inversion / BTRS switch at n p = 56
                                  (560, 0.0999), (560, 0.1), (114, 0.49), (115, 0.49), (1600, 0.035), (500, 0.112),
-                                 (130, 0.43), (150, 0.627), (152, 0.63)])
+                                 (130, 0.43), (150, 0.627), (152, 0.63),
+                                 # inversion with q^n below the normal fp32 range (scaled start), and
+                                 # around the inversion / BTRS switch at n p = 80
+                                 (140, 0.5), (158, 0.5), (161, 0.5), (400, 0.19), (186, 0.43), (800, 0.0999),
+                                 (800, 0.1), (2300, 0.0347), (216, 0.63), (218, 0.634)])
 def test_binomial(n, p):
     N = 300000
     s = oracle.sample(oracle.SMP_BINOMIAL, N, seed=23, i0=n, f0=p)
