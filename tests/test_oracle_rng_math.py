@@ -1,7 +1,8 @@
 """Pins for the oracle's random-number layer and elementary functions.
 
-* Philox4x32-10 is checked against an independent implementation: PyTorch's C++
-  PhiloxRNGEngine header, compiled here into a tiny helper.
+* Philox4x32-10 is checked against two independent implementations: PyTorch's C++
+  PhiloxRNGEngine header and rocRAND's Philox4x32-10 header, each compiled here into a tiny
+  helper.
 * The uniform map u = (2*(x>>9)+1) 2^-24 is checked exhaustively over its 2^23 classes.
 * The fp32 log/log1p/exp/expm1 written from their series are checked against fp64
   numpy on dense grids to a stated ulp bound.
@@ -57,6 +58,44 @@ def test_philox_matches_independent_implementation(aten_philox):
     ref = np.array([[int(t) for t in ln.split()] for ln in res.strip().splitlines()], dtype=np.uint32)
     got = oracle.philox(ctr, key)
     assert np.array_equal(got, ref)
+
+
+ROCRAND_SRC = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+// rocRAND's own ten-round Philox4x32 block function on a given counter and key
+struct Block : rocrand_device::philox4x32_10_engine {
+  uint4 at(uint4 c, uint2 k) { return ten_rounds(c, k); }
+};
+int main() {
+  unsigned c0, c1, c2, c3, k0, k1;
+  Block b;
+  while (scanf("%u %u %u %u %u %u", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+    uint4 c; c.x = c0; c.y = c1; c.z = c2; c.w = c3;
+    uint2 k; k.x = k0; k.y = k1;
+    uint4 r = b.at(c, k);
+    printf("%u %u %u %u\n", r.x, r.y, r.z, r.w);
+  }
+}
+"""
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="needs hipcc for rocRAND's header")
+def test_philox_matches_rocrand(tmp_path):
+    """A second independent implementation: rocRAND's Philox4x32-10 block function (its source
+    header, compiled here for the host), on random counters and keys and on the counters the
+    simulator uses."""
+    src, exe = str(tmp_path / "rr.cpp"), str(tmp_path / "rr")
+    open(src, "w").write(ROCRAND_SRC)
+    subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-o", exe, src], check=True, capture_output=True)
+    rng = np.random.default_rng(13)
+    ctr = rng.integers(0, 2**32, size=(2000, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(2000, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[:4] = [[0, 0, 0, 0], [3, 7, 19999, (2 << 24) | 5], [4095, 999, 0, 1 << 24], [0xFFFFFFFF] * 4]
+    lines = "\n".join(" ".join(str(int(v)) for v in (*c, *k)) for c, k in zip(ctr, key))
+    res = subprocess.run([exe], input=lines, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(t) for t in ln.split()] for ln in res.strip().splitlines()], dtype=np.uint32)
+    assert np.array_equal(oracle.philox(ctr, key), ref)
 
 
 def test_uniform_map_exhaustive():
