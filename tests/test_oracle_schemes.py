@@ -168,6 +168,33 @@ def test_argument3_gap_equals_forward_departures():
     assert dK.mean() < lam * h + 0.05
 
 
+@pytest.mark.parametrize("lam,mu,c,h", [(6.0, 1.0, 5, 0.3), (3.0, 2.0, 2, 0.1), (9.0, 1.0, 12, 0.5)])
+def test_argument2_transient_stochastic_order(lam, mu, c, h):
+    """Argument 2 (single station, from empty): N^f_tau <= N_tau <= N^b_tau in first-order
+    stochastic dominance at every step.  The exact laws of the two Euler chains (the kernels the
+    oracle's runs are pinned to) against the exact law of the M/M/c queue at tau h, from the
+    matrix exponential of its generator: the tail probabilities are ordered at every level."""
+    nmax = 160
+    b, f = euler_kernels(lam, mu, c, h, nmax)
+    G = np.zeros((nmax + 1, nmax + 1))
+    for y in range(nmax + 1):
+        if y < nmax:
+            G[y, y + 1] = lam
+        if y > 0:
+            G[y, y - 1] = min(y, c) * mu
+        G[y, y] = -G[y].sum()
+    step = scipy.linalg.expm(G * h)
+    pb = pf = pt = np.eye(nmax + 1)[0]
+    for _ in range(30):
+        pb, pf, pt = pb @ b, pf @ f, pt @ step
+        assert pt[-10:].sum() < 1e-9
+        tail = lambda p: p[::-1].cumsum()[::-1]          # P(N >= x), x = 0..nmax
+        assert np.all(tail(pf) <= tail(pt) + 1e-12) and np.all(tail(pt) <= tail(pb) + 1e-12)
+    # the ordering is strict in the mean, and the gap is of order lambda h
+    mean = lambda p: float(p @ np.arange(nmax + 1))
+    assert mean(pf) < mean(pt) < mean(pb) and mean(pb) - mean(pf) <= c * mu * h + 1e-9
+
+
 def stationary_mean(T):
     """Mean of the stationary law of a finite transition matrix."""
     w, v = scipy.linalg.eig(T.T)
