@@ -69,18 +69,26 @@ __device__ __forceinline__ bool task_of(const NetView &v, TaskPos &tp) {
 }
 
 // Task (s, t) covers statistics tiles 2t and 2t + 1 (the second is absent when the last task
-// holds 32 replications or fewer); each belongs to this task alone within a launch.
+// holds 32 replications or fewer); each belongs to this task alone within a launch.  The sums
+// are added with atomics whose result is not read: integer adds in any order give the same
+// sums, and the task does not wait for a load of the old value (1.4 % on the 1000-station step).
 __device__ __forceinline__ void add_tile_stats(const NetView &v, int s, int t, int xn, int xq, int xd,
                                                int lane) {
   const long long vn = half_sum(xn), vq = half_sum(xq), vd = half_sum(xd);
   const int st = 2 * t + (lane >> 5);
   if ((lane & 31) == 0 && st < v.stiles) {
     const long long plane = (long long)v.n * v.stiles;
-    long long *p = v.tsums + (long long)s * v.stiles + st;
-    p[0] += vn;
-    p[plane] += vq;
-    p[2 * plane] += vd;
+    unsigned long long *p = reinterpret_cast<unsigned long long *>(v.tsums + (long long)s * v.stiles + st);
+    atomicAdd(p, (unsigned long long)vn);
+    atomicAdd(p + plane, (unsigned long long)vq);
+    atomicAdd(p + 2 * plane, (unsigned long long)vd);
   }
+}
+
+// Score runs: adds (N - m)^+ to the replication's int64 sum (an atomic whose result is not read,
+// like the statistics sums: the same sum, no wait for the old value).
+__device__ __forceinline__ void add_sumq(long long *sq, int q) {
+  if (q) atomicAdd(reinterpret_cast<unsigned long long *>(sq), (unsigned long long)q);
 }
 
 // One (station s, tile t) task of step tau.  SCORE runs also add each lane's draw scores
@@ -149,7 +157,7 @@ __device__ __forceinline__ void sweep_task(const NetView &v, int s, int t, int t
       *Nrow = xn;
       q = max(xn - m, 0);
     }
-    if (SCORE && (SCHEME == 1 || tau >= 2)) v.sq[(long long)s * reps + rep] += q;
+    if (SCORE && (SCHEME == 1 || tau >= 2)) add_sumq(v.sq + (long long)s * reps + rep, q);
     if (REC) {
       const int rt = tau - v.rec_t0;
       const int rn = SCHEME == 0 ? rt - 1 : rt;     // the step whose end state xn is
@@ -197,7 +205,7 @@ __device__ __forceinline__ void finish_task(const NetView &v, int s, int t, unsi
     *Nrow = x;
     q = v.K > 0 ? max(x - servers_in(v.segidx, v.seg_m, v.n, s, v.K - 1, v.sp[s].c), 0) : 0;
     if (x >= kStateLimit) atomicOr(dflags, 1u);
-    if (SCORE && v.K > 0) v.sq[(long long)s * v.reps + rep] += q;
+    if (SCORE && v.K > 0) add_sumq(v.sq + (long long)s * v.reps + rep, q);
     if (REC) {
       const int rn = v.K - v.rec_t0;
       if (v.K > 0 && rn >= 0 && rn < v.rec_len) v.rec_N[((long long)rn * v.n + s) * v.reps + rep] = x;
