@@ -113,15 +113,24 @@ __device__ __forceinline__ void sweep_task(const NetView &v, int s, int t, int t
   if (valid) {
     const uint32_t grep = (uint32_t)(v.rep0 + rep);
     int *Nrow = v.N + (long long)s * reps + rep;
+    // Score runs: this lane owns its replication's score sums for the launch, so their old
+    // values are read here, before the task stores anything, and the loads overlap the draws.
+    float *sm = nullptr, *sl = nullptr;
+    float sm0 = 0.0f, sl0 = 0.0f;
+    if (SCORE) {
+      sm = v.smu + (long long)s * reps + rep;
+      sm0 = *sm;
+      if (p.lam0 > 0.0f) {
+        sl = v.slam + (long long)v.scp[s].src * reps + rep;
+        sl0 = *sl;
+      }
+    }
     int A = 0;
     if (p.lam0 > 0.0f) {
       Stream S = make_stream(v.k0, v.k1, grep, (uint32_t)s, (uint32_t)(tau - 1), SUB_ARR);
       const float gt = v.g[tau - 1];
       A = poisson(p.lam0 * gt, S, flags);
-      if (SCORE) {
-        float *sl = v.slam + (long long)v.scp[s].src * reps + rep;
-        *sl = *sl + ((float)A / p.lam0 - gt);
-      }
+      if (SCORE) *sl = sl0 + ((float)A / p.lam0 - gt);
     }
     const int slot = SCHEME == 0 ? ((tau - 1) & 1) : (tau % ring.depth);
     int *in = v.ring + ((long long)ring.off + slot) * reps + rep;
@@ -141,10 +150,7 @@ __device__ __forceinline__ void sweep_task(const NetView &v, int s, int t, int t
         float sc;
         D = dep_mode == 1 ? gendep_naive_score(x, m, p.mudt, p.mu, dt, S, flags, sc)
                           : gendep_score(x, m, p.mu, dt, v.dep[s], rate, v.scp[s].kap, S, flags, sc);
-        if (x > 0) {
-          float *sm = v.smu + (long long)s * reps + rep;
-          *sm = *sm + sc;
-        }
+        if (x > 0) *sm = sm0 + sc;
       } else {
         D = dep_mode == 1 ? gendep_naive(x, m, p.mudt, S, flags)
                           : gendep(x, m, p.mu, dt, v.dep[s], rate, S, flags);
