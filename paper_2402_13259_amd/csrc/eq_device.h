@@ -34,9 +34,11 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
     U4 n;
-    n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    // Three-way xors as one gfx950 bitop3 each (truth table 0x96), which the compiler
+    // does not form by itself here.
+    n.x = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96);
     n.y = (uint32_t)p1;
-    n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    n.z = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96);
     n.w = (uint32_t)p0;
     c = n;
     k0 += 0x9E3779B9u;
@@ -307,8 +309,7 @@ __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, ui
         // No branches: a lane that has stopped keeps only its k; its f and F run on unused.
         const float fn = f * (g * ivs[j] - r);
         const float Fn = F + fn;
-        const int kj = base + j + 1;
-        k = go ? kj : k;
+        k += go ? 1 : 0;   // a searching lane is at k = base + j
         go = go && Fn != F && u > Fn;   // Fn == F: the pmf no longer moves the sum
         f = fn;
         F = Fn;
@@ -319,7 +320,7 @@ __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, ui
         const float fn = f * (g * ivs[j] - r);
         const float Fn = F + fn;
         const int kj = base + j + 1;
-        k = go ? kj : k;
+        k += go ? 1 : 0;
         go = go && Fn != F && u > Fn && kj < kmax;
         f = fn;
         F = Fn;

@@ -120,6 +120,16 @@ inline uint64_t emu_ballot(bool pred) { return pred ? 1ull << (threadIdx.x & 63)
 #define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane((uint32_t)(v))
 #define __builtin_amdgcn_ballot_w64(p) emu_ballot((bool)(p))
 
+// gfx950's three-input bitwise operation: bit i of the truth table is the result for the
+// input bits (a, b, c) = (i >> 2 & 1, i >> 1 & 1, i & 1).
+inline uint32_t emu_bitop3(uint32_t a, uint32_t b, uint32_t c, unsigned table) {
+  uint32_t out = 0;
+  for (unsigned i = 0; i < 8; ++i)
+    if (table >> i & 1u) out |= ((i & 4u) ? a : ~a) & ((i & 2u) ? b : ~b) & ((i & 1u) ? c : ~c);
+  return out;
+}
+#define __builtin_amdgcn_bitop3_b32(a, b, c, t) emu_bitop3((uint32_t)(a), (uint32_t)(b), (uint32_t)(c), (unsigned)(t))
+
 // HIP's integer min / max of device code
 inline int min(int a, int b) { return a < b ? a : b; }
 inline int max(int a, int b) { return a > b ? a : b; }
