@@ -418,7 +418,8 @@ int32_t orc_poisson(float lam, ustream *S)
 /* raised by sc = -120 - e when e < -120 (q^n below the normal fp32 range), and the  */
 /* uniform raised by the same 2^sc.  Scaling by a power of two is exact, so every    */
 /* step and comparison is the one an fp32 without the lower exponent limit makes;    */
-/* sc = 0 for n p < 56, where q^n >= e^-78 is a normal number anyway.                */
+/* sc = 0 for n p < 56, where q^n >= e^-78 is a normal number anyway.  The factor   */
+/* of the pmf recurrence, (n+1) r / k - r, is one fma of g = (n+1) r and fp32 1/k.  */
 static int32_t binom_inversion(int32_t n, float p, ustream *S)
 {
     float q = 1.0f - p;
@@ -438,7 +439,7 @@ static int32_t binom_inversion(int32_t n, float p, ustream *S)
     while (u > F && k < n && k < BINOM_INV_MAX) {
         EV(EV_BIN_INV_STEP);
         k += 1;
-        f = f * (g * INV[k] - r);                     /* f_k = f_{k-1} (n-k+1)/k p/q */
+        f = f * fmaf(g, INV[k], -r);                  /* f_k = f_{k-1} (n-k+1)/k p/q */
         float Fn = F + f;
         if (Fn == F) break;
         F = Fn;

@@ -276,7 +276,8 @@ __device__ __forceinline__ int poisson(float lam, Stream &S, uint32_t &flags) {
 }
 
 // Binomial(n, p), n p < 80, 0 < p <= 1/2: inversion from 0 with the pmf recurrence
-// f_k = f_{k-1} ((n+1) r / k - r), r = p/q, f_0 = e^{n lq}, lq = ln(1 - p), at most 255 steps
+// f_k = f_{k-1} ((n+1) r / k - r), r = p/q, the factor one fma of g = (n+1) r and the fp32
+// reciprocal of k, f_0 = e^{n lq}, lq = ln(1 - p), at most 255 steps
 // (P(X > 255) < 1e-40).  f_0 is formed as ex() forms it, exp(r) 2^e with n lq = e ln 2 + r, but
 // with the binary exponent raised by sc = -120 - e when e < -120 (f_0 below the normal fp32
 // range; n lq > -111 here), and the uniform raised by the same 2^sc: scaling by a power of two is
@@ -307,7 +308,7 @@ __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, ui
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         // No branches: a lane that has stopped keeps only its k; its f and F run on unused.
-        const float fn = f * (g * ivs[j] - r);
+        const float fn = f * fma32(g, ivs[j], -r);
         const float Fn = F + fn;
         k += go ? 1 : 0;   // a searching lane is at k = base + j
         go = go && Fn != F && u > Fn;   // Fn == F: the pmf no longer moves the sum
@@ -317,7 +318,7 @@ __device__ __forceinline__ int binom_inv(int n, float r, float lq, Stream &S, ui
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float fn = f * (g * ivs[j] - r);
+        const float fn = f * fma32(g, ivs[j], -r);
         const float Fn = F + fn;
         const int kj = base + j + 1;
         k += go ? 1 : 0;

@@ -66,9 +66,10 @@ def event_costs(p: dict) -> dict:
         # every binomial draw: n <= 0, n p < 80 (cvt, mul, cmp), the flip n - k
         "binomial_call": 5,
         # inversion: g = r (n + 1), f0 = e^{n lq} (the exponential's steps, with the exponent scale:
-        # its test, the offset, the uniform's factor), kmax, go;  step: f (g / k - r), F + f, k, two tests
+        # its test, the offset, the uniform's factor), kmax, go;  step: f fma(g, 1/k, -r), F + f, k,
+        # two tests
         "bin_inv": 3 + 1 + p["ex"] + 4 + 1 + 2,
-        "bin_inv_step": 7,
+        "bin_inv_step": 6,
         # BTRS set-up (spq, b, a, c, alpha, vr, mode, nm, the mode's log-ratio and Stirling terms)
         "btrs": 30 + p["sqrt"] + 3 * p["div"] + p["floor"] + p["fma64"] + L1P + 2 * ST,
         # attempt: us, candidate k = floor((2a / us + b) u + c), the squeeze test

@@ -85,7 +85,7 @@ MUTANTS = {
     # samplers
     "poisson_inversion_index": ([("p = p * (lam * INV[k]);", "p = p * (lam * INV[k + 1]);")], "sampler"),
     "ptrs_log_sign": ([("- 0.5f * loglam - HALF_LOG_2PI", "+ 0.5f * loglam - HALF_LOG_2PI")], "sampler"),
-    "binomial_recurrence_sign": ([("f = f * (g * INV[k] - r);", "f = f * (g * INV[k] + r);")], "sampler"),
+    "binomial_recurrence_sign": ([("f = f * fmaf(g, INV[k], -r);", "f = f * fmaf(g, INV[k], r);")], "sampler"),
     "binomial_start": ([("float x = (float)n * orc_log1pf(-p);", "float x = -(float)n * p;")], "sampler"),
     "binomial_unscaled_uniform": ([("float u = us_u01(S) * f_from_bits((uint32_t)(sc + 127) << 23);",
                                     "float u = us_u01(S);")], "sampler"),
