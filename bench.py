@@ -40,8 +40,8 @@ sys.path.insert(0, ROOT)
 #   slots  = issued VALU lane slots per station-step = SQ_INSTS_VALU * 64 / station-steps
 #   bytes  = HBM bytes per station-step = (2.0 * FETCH_SIZE + 1.0 * WRITE_SIZE) / station-steps,
 #            the factors from a plain 1 GiB device copy measured with the same counters.
-KERNEL_COUNTERS = {"sources_sha256_16": "8e748774d897ce5b", "active_lane_ops_per_station_step": 1060.4,
-                   "issued_lane_slots_per_station_step": 1854.7, "traffic_bytes_per_station_step": 33.08}
+KERNEL_COUNTERS = {"sources_sha256_16": "67e2240bfba9a089", "active_lane_ops_per_station_step": 960.4,
+                   "issued_lane_slots_per_station_step": 1680.2, "traffic_bytes_per_station_step": 33.08}
 # The algorithm's own operations per station-step: the oracle's event counts on this workload
 # (tests/golden/op_counts_dag1000.json) priced with the VALU instruction counts of each sampler
 # building block in the gfx950 build (tests/isa/op_costs_gfx950.json).
