@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 #   slots  = issued VALU lane slots per station-step = SQ_INSTS_VALU * 64 / station-steps
 #   bytes  = HBM bytes per station-step = (2.0 * FETCH_SIZE + 1.0 * WRITE_SIZE) / station-steps,
 #            the factors from a plain 1 GiB device copy measured with the same counters.
-KERNEL_COUNTERS = {"sources_sha256_16": "67e2240bfba9a089", "active_lane_ops_per_station_step": 960.4,
+KERNEL_COUNTERS = {"sources_sha256_16": "333cf0b41667b8b9", "active_lane_ops_per_station_step": 960.4,
                    "issued_lane_slots_per_station_step": 1680.2, "traffic_bytes_per_station_step": 33.08}
 # The algorithm's own operations per station-step: the oracle's event counts on this workload
 # (tests/golden/op_counts_dag1000.json) priced with the VALU instruction counts of each sampler

@@ -386,7 +386,8 @@ int eq_batch_check(eq_batch *batch, void *stream);
 /* ---- diagnostics: the device building blocks, for parity tests against a reference ---- */
 
 /* y[i] = f(x[i]) with the library's device fp32 function: kind 0 log, 1 log1p, 2 exp,
- * 3 expm1.  x, y device float [count]. */
+ * 3 expm1, 4 the uniform (2 (b >> 9) + 1) 2^-24 of the 32-bit word b with the bits of x[i]
+ * (the samplers' map from a Philox output word to (0, 1)).  x, y device float [count]. */
 int eq_selftest_math(int32_t kind, const float *d_x, float *d_y, int64_t count, void *stream);
 
 /* Draw count samples; sample s uses the uniform stream (rep0 + s, station, step0, sub) with

@@ -356,7 +356,8 @@ def op_counts(reset: bool = True) -> dict:
 
 
 def math_fn(kind: int, x: np.ndarray) -> np.ndarray:
-    """kind 0 log, 1 log1p, 2 exp, 3 expm1 (the oracle's own fp32 functions)."""
+    """kind 0 log, 1 log1p, 2 exp, 3 expm1 (the oracle's own fp32 functions); 4 the uniform
+    orc_u01 of the 32-bit word with each element's bits."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     y = np.zeros_like(x)
     lib().orc_math(kind, x.size, _ptr(x), _ptr(y))

@@ -1217,6 +1217,12 @@ int orc_math(int32_t kind, int64_t count, const float *x, float *y)
         case 1: y[i] = orc_log1pf(x[i]); break;
         case 2: y[i] = orc_expf(x[i]); break;
         case 3: y[i] = orc_expm1f(x[i]); break;
+        case 4: {
+            uint32_t b;
+            memcpy(&b, &x[i], sizeof b);
+            y[i] = orc_u01(b);
+            break;
+        }
         default: return ORC_EINVAL;
         }
     }

@@ -428,7 +428,8 @@ def station_stats(net: Net, res: RunResult, init=None, stream=None):
 
 
 def selftest_math(kind: int, x):
-    """eq_selftest_math: the device log (0), log1p (1), exp (2) or expm1 (3) of every element of x."""
+    """eq_selftest_math: the device log (0), log1p (1), exp (2) or expm1 (3) of every element of x,
+    or (4) the uniform the samplers take from the 32-bit word with the element's bits."""
     import torch
     _dev(x, torch.float32, None, "x")
     y = torch.empty_like(x)

@@ -1191,7 +1191,7 @@ int eq_sim_check(eq_net *net, void *stream) {
 }
 
 int eq_selftest_math(int32_t kind, const float *d_x, float *d_y, int64_t count, void *stream) {
-  if (kind < 0 || kind > 3 || count < 0 || (count > 0 && (!d_x || !d_y))) return fail(EQ_EINVAL, "bad arguments");
+  if (kind < 0 || kind > 4 || count < 0 || (count > 0 && (!d_x || !d_y))) return fail(EQ_EINVAL, "bad arguments");
   int dev = 0;
   int rc = ensure_device(&dev);
   if (rc) return rc;

@@ -296,7 +296,8 @@ __global__ void k_selftest_math(int kind, const float *x, float *y, long long co
     case 0: r = ln(v); break;
     case 1: r = ln1p(v); break;
     case 2: r = ex(v); break;
-    default: r = exm1(v); break;
+    case 3: r = exm1(v); break;
+    default: r = to_unit(__float_as_uint(v)); break;
   }
   y[i] = r;
 }

@@ -1,6 +1,7 @@
 """The device's elementary functions against the oracle's on every fp32 input of the domain
 the samplers use them on: log on all positive floats, log1p on x > -1, exp and expm1 on all
-finite floats.  Outputs must be bit-identical (NaN compared as NaN)."""
+finite floats; and the map from a Philox output word to a uniform on all 2^32 words.  Outputs
+must be bit-identical (NaN compared as NaN)."""
 import os
 from concurrent.futures import ThreadPoolExecutor
 
@@ -14,8 +15,9 @@ pytestmark = pytest.mark.gpu
 POS = (0x00000000, 0x7F800000)          # +0 .. largest finite
 NEG_TO_M1 = (0x80000000, 0xBF800000)    # -0 .. -(1 - 2^-24)
 NEG = (0x80000000, 0xFF800000)          # -0 .. most negative finite
-DOMAINS = {0: [(0x00000001, 0x7F800000)], 1: [POS, NEG_TO_M1], 2: [POS, NEG], 3: [POS, NEG]}
-NAMES = {0: "log", 1: "log1p", 2: "exp", 3: "expm1"}
+DOMAINS = {0: [(0x00000001, 0x7F800000)], 1: [POS, NEG_TO_M1], 2: [POS, NEG], 3: [POS, NEG],
+           4: [(0x00000000, 0x100000000)]}
+NAMES = {0: "log", 1: "log1p", 2: "exp", 3: "expm1", 4: "uniform"}
 CHUNK = 1 << 28
 
 
@@ -27,7 +29,7 @@ def eb():
     return binding
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
 def test_math_exhaustive(eb, kind):
     import torch
     workers = min(16, os.cpu_count() or 1)

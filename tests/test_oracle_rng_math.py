@@ -108,6 +108,10 @@ def test_uniform_map_exhaustive():
     assert np.array_equal(u.astype(np.float64), expect)          # exact
     assert u.min() == np.float32(2.0 ** -24) and u.max() == np.float32(1 - 2.0 ** -24)
     assert np.all(np.diff(u) > 0)                                # strictly increasing, never 0 or 1
+    # the C function the samplers call, on the same words and with random low bits
+    low = np.random.default_rng(5).integers(0, 512, size=j.size, dtype=np.uint32)
+    for words in (x, x | low):
+        assert np.array_equal(oracle.math_fn(4, words.view(np.float32)).astype(np.float64), expect)
 
 
 def _ulp_err(got32, ref64):
