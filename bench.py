@@ -47,6 +47,8 @@ KERNEL_COUNTERS = {"sources_sha256_16": "333cf0b41667b8b9", "active_lane_ops_per
 # building block in the gfx950 build (tests/isa/op_costs_gfx950.json).
 OP_COUNTS_JSON = os.path.join(ROOT, "tests", "golden", "op_counts_dag1000.json")
 OP_COSTS_JSON = os.path.join(ROOT, "tests", "isa", "op_costs_gfx950.json")
+# The same events at the instruction costs of the first priced build, held fixed.
+OP_COSTS_FIXED_JSON = os.path.join(ROOT, "tests", "isa", "op_costs_gfx950_first.json")
 KERNEL_SOURCES = ["paper_2402_13259_amd/csrc/eq_device.h", "paper_2402_13259_amd/csrc/eq_internal.h",
                   "paper_2402_13259_amd/csrc/eq_sweep.h", "paper_2402_13259_amd/csrc/eq_kernels.hip"]
 # VALU peak for the kernel's (non-packed) instructions: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -56,11 +58,11 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_ops() -> float:
+def algorithmic_ops(costs_json: str = OP_COSTS_JSON) -> float:
     """Operations per station-step of the benchmark step (the mean of its two schemes)."""
     sys.path.insert(0, os.path.join(ROOT, "tests", "isa"))
     import op_costs
-    costs = json.load(open(OP_COSTS_JSON))["events"]
+    costs = json.load(open(costs_json))["events"]
     counts = json.load(open(OP_COUNTS_JSON))
     return 0.5 * sum(op_costs.algorithmic_ops(counts[s], costs) for s in ("backward", "forward"))
 
@@ -229,6 +231,11 @@ def main():
                 ops_basis="the algorithm's operations: oracle event counts on this workload (Philox blocks, "
                           "uniforms, sampler set-ups, search steps, rejection attempts, routed edges) x VALU "
                           "instructions of each building block in the gfx950 build")
+    fixed = algorithmic_ops(OP_COSTS_FIXED_JSON)
+    roof["fixed_prices"] = {"ops_per_station_step": round(fixed, 1),
+                            "frac": round(fixed * ss_per_launch / launch_s / 1e12 / VALU_PEAK_TOPS, 4),
+                            "basis": "the same event counts at the instruction costs of the first priced build "
+                                     "(tests/isa/op_costs_gfx950_first.json), held fixed across builds"}
     if sources_hash() == KERNEL_COUNTERS["sources_sha256_16"]:
         act = KERNEL_COUNTERS["active_lane_ops_per_station_step"]
         slots = KERNEL_COUNTERS["issued_lane_slots_per_station_step"]

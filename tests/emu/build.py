@@ -6,6 +6,7 @@ array (`extern __shared__ T name[];`) becomes a pointer to the workgroup's emula
 The result, tests/emu/_build/libeulerq_emu.so, exports the same C ABI as libeulerq.so; it must
 be loaded into a process that has the ASan runtime preloaded (see `asan_env`).
 """
+import fcntl
 import hashlib
 import os
 import re
@@ -40,7 +41,16 @@ def _stamp() -> str:
 
 
 def build(force: bool = False) -> str:
-    """Compile (if the sources changed) and return the path of the emulated library."""
+    """Compile (if the sources changed) and return the path of the emulated library.  Processes
+    that call this together (parallel test workers) build one at a time; the later ones find the
+    library current."""
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "lock"), "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        return _build_locked(force)
+
+
+def _build_locked(force: bool) -> str:
     stamp_path = os.path.join(OUT, "stamp")
     stamp = _stamp()
     if not force and os.path.exists(LIB) and os.path.exists(stamp_path) and open(stamp_path).read() == stamp:

@@ -285,7 +285,21 @@ def case_noalloc():
     assert b"bytes of scratch" in F["eq_last_error"]()
 
 
-CASES = {"noalloc": case_noalloc, "record_sojourn": case_record_sojourn, "kernels": case_kernels, "scores": case_scores, "batch": case_batch,
+def case_stalls():
+    """Binomial inversion draws whose fp32 cdf sum stops moving below the largest uniform, the
+    stop at each of the four positions of a pass of four steps (eq_selftest_sample), against the
+    oracle; every case has draws that end at the stop."""
+    for n, p, k_stop in [(168, 0.437955766916275, 109), (426, 0.17230048775672913, 118),
+                         (192, 0.36172786355018616, 107), (283, 0.23832014203071594, 108)]:
+        count = 1 << 21
+        out = np.zeros(count, np.float32)
+        check(F["eq_selftest_sample"](1, count, 321, 0, 5, 2, 2, n, 0, p, 0.0, 0.0, 0.0, ptr(out), None))
+        r = oracle.sample(1, count, seed=321, rep0=0, station=5, step0=2, sub=2, i0=n, f0=p)
+        assert (r == k_stop).sum() >= 1, (n, p)
+        assert np.array_equal(out.view(np.uint32), r.view(np.uint32)), (n, p)
+
+
+CASES = {"stalls": case_stalls, "noalloc": case_noalloc, "record_sojourn": case_record_sojourn, "kernels": case_kernels, "scores": case_scores, "batch": case_batch,
          "oracle": case_oracle}
 
 if __name__ == "__main__":

@@ -53,3 +53,6 @@ def test_algorithmic_operation_count():
     counts = json.load(open(bench.OP_COUNTS_JSON))
     assert counts["workload"] == "dag1000" and counts["K"] == 20000
     assert 700.0 < ops < 1000.0
+    # the same events at the fixed prices of the first priced build: no build since is dearer
+    fixed = bench.algorithmic_ops(bench.OP_COSTS_FIXED_JSON)
+    assert ops <= fixed < 1000.0

@@ -69,3 +69,7 @@ def test_oracle_sanitized(emu_env, tmp_path):
 
 def test_allocation_free_entry_point_sanitized(emu_env):
     run_case(emu_env, "noalloc")
+
+
+def test_stalled_inversion_sums_sanitized(emu_env):
+    run_case(emu_env, "stalls")

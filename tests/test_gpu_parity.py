@@ -124,6 +124,22 @@ def test_binomial_inversion_cap(eb, n, p):
     assert g.max() <= n
 
 
+# Binomials whose fp32 cdf sum stops moving below the largest uniform, 1 - 2^-24: a draw above
+# the final sum ends at the step that no longer moves it (the same k for every such draw), which
+# falls at each of the four positions of a pass of four steps (k mod 4 = 1, 2, 3, 0).
+STALL_CASES = [(168, 0.437955766916275, 109), (426, 0.17230048775672913, 118), (192, 0.36172786355018616, 107),
+               (283, 0.23832014203071594, 108)]
+
+
+@pytest.mark.parametrize("n,p,k_stop", STALL_CASES)
+def test_binomial_inversion_stalled_sum(eb, n, p, k_stop):
+    count = 1 << 22
+    g = eb.selftest_sample(1, count, seed=321, rep0=0, station=5, step0=2, sub=2, i0=n, f0=p).cpu().numpy()
+    r = oracle.sample(1, count, seed=321, rep0=0, station=5, step0=2, sub=2, i0=n, f0=p)
+    assert (r == k_stop).sum() >= 5        # the stopped-sum ending is exercised
+    assert np.array_equal(g.view(np.uint32), r.view(np.uint32))
+
+
 # ---------------------------------------------------------------------------------------
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("scheme", [0, 1])
